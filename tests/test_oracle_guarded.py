@@ -1,0 +1,370 @@
+"""Pins for the oracle's guarded kernels and first-fault log (CPU only).
+
+* vectorized forms against the per-access loops on hostile scenarios;
+* every denial enumerated by a recording log: count exact, first = minimum key;
+* no-fault copy / gather against plain library routines;
+* triad against exact rational arithmetic with an independent round-to-nearest-even;
+* scatter-add with unit gradients against integer counts (np.bincount);
+* protected canary bytes never change; suppressed loads read zero.
+"""
+import copy
+import random
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import RangeTable, USER, PROTECTED, MMIO, ALLOW, V_PROTECTED, V_STRADDLE, \
+    V_UNMAPPED, V_CROSS_ALLOC
+from oracle.memory import Memory
+from oracle import guarded as G
+
+
+class RecordingLog(G.FaultLog):
+    """Keeps every denial; pins FaultLog's count and minimum-key bookkeeping."""
+
+    def __init__(self):
+        super().__init__()
+        self.all = []
+
+    def offer(self, table, seq, elem, operand, A, w, op, n=1):
+        assert n == 1
+        self.all.append((seq, elem, operand, A, w, op))
+        super().offer(table, seq, elem, operand, A, w, op, n)
+
+
+BASE = 0x7000_0000
+
+
+def scenario(seed):
+    """A table with backed USER allocations A, B (adjacent), C, a protected canary P,
+    an MMIO range M and holes; returns (table, memory, named addresses)."""
+    rng = np.random.default_rng(seed)
+    t = RangeTable()
+    mem = Memory()
+    addr = {}
+
+    def user(name, base, size):
+        t.insert(base, size, USER)
+        mem.add(base, rng.integers(0, 256, size, dtype=np.uint8))
+        addr[name] = (base, base + size)
+
+    user("A", BASE, 512)
+    user("B", BASE + 512, 384)                    # adjacent to A
+    t.insert(BASE + 896, 128, PROTECTED)           # canary, backed so we can check it
+    mem.add(BASE + 896, np.full(128, 0xA5, np.uint8))
+    addr["P"] = (BASE + 896, BASE + 1024)
+    user("C", BASE + 2048, 1000)                   # hole [1024, 2048) before it
+    t.insert(BASE + 4096, 64, MMIO)
+    addr["M"] = (BASE + 4096, BASE + 4160)
+    user("I", BASE + 8192, 8 * 64)                 # index buffer
+    return t, mem, addr
+
+
+def pointer_choices(addr):
+    A, B, C, P, M = addr["A"], addr["B"], addr["C"], addr["P"], addr["M"]
+    return [A[0], A[0] + 13, A[1] - 40, B[0], B[1] - 1, C[0] + 4, C[1] - 100,
+            P[0] + 8, M[0], BASE + 1500, BASE - 64, 0]
+
+
+def _same(memA, memB, addr):
+    for k in ("A", "B", "C", "P", "I"):
+        lo, hi = addr[k]
+        assert memA.read(lo, hi - lo) == memB.read(lo, hi - lo), k
+
+
+def _overlap(p, n, q, m):
+    """Partially overlapping operands give order-dependent results (like memcpy); the
+    API leaves them unspecified, so the pins skip them (identical pointers are fine for
+    elementwise ops)."""
+    return p != q and n > 0 and m > 0 and p < q + m and q < p + n
+
+
+def _logs_equal(la, lb):
+    assert la.count == lb.count
+    assert la.first == lb.first
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_copy_vec_matches_loop(seed):
+    t, mem, addr = scenario(seed)
+    rng = random.Random(seed)
+    ptrs = pointer_choices(addr)
+    for trial in range(40):
+        dst, src = rng.choice(ptrs), rng.choice(ptrs)
+        n = rng.choice([0, 1, 7, 64, 300, 700])
+        if _overlap(dst, n, src, n) or (dst == src and n):
+            continue
+        m1, m2 = copy.deepcopy(mem), copy.deepcopy(mem)
+        l1, l2 = RecordingLog(), G.FaultLog()
+        G.copy_loop(t, m1, l1, trial, dst, src, n)
+        G.copy_vec(t, m2, l2, trial, dst, src, n)
+        _same(m1, m2, addr)
+        _logs_equal(l1, l2)
+        assert l1.count == len(l1.all)
+        if l1.all:
+            assert min((a[0], a[1], a[2]) for a in l1.all) == l1.key()
+        # protected canary never changes
+        assert m1.read(*addr["P"][:1], 128) == bytes([0xA5]) * 128
+
+
+def test_copy_no_fault_is_plain_copy():
+    t, mem, addr = scenario(1)
+    src = addr["C"][0]
+    dst = addr["A"][0]
+    want = mem.read(src, 500)
+    log = G.FaultLog()
+    G.copy_vec(t, mem, log, 0, dst, src, 500)
+    assert mem.read(dst, 500) == want and log.count == 0 and log.first is None
+
+
+def test_copy_partial_closed_form_values():
+    t, mem, addr = scenario(2)
+    src = addr["A"][1] - 10          # 10 readable bytes, then B (another allocation)
+    dst = addr["C"][0]
+    before = mem.read(dst, 40)
+    want = mem.read(src, 10) + bytes(30)
+    log = G.FaultLog()
+    G.copy_vec(t, mem, log, 5, dst, src, 40)
+    assert mem.read(dst, 40) == want
+    assert before != want
+    assert log.count == 30
+    f = log.first
+    assert (f["seq"], f["elem"], f["operand"]) == (5, 10, 0)
+    assert f["addr"] == addr["B"][0] and f["verdict"] == V_CROSS_ALLOC and f["owner"] == 1
+    # copy into the protected canary: every store dropped, reason PROTECTED
+    log.clear()
+    G.copy_vec(t, mem, log, 6, addr["P"][0], addr["A"][0], 16)
+    assert log.count == 16 and log.first["verdict"] == V_PROTECTED
+    assert log.first["operand"] == 1 and log.first["elem"] == 0
+    assert mem.read(addr["P"][0], 16) == bytes([0xA5]) * 16
+
+
+def test_suppress_only_policy_logs_nothing():
+    t, mem, addr = scenario(3)
+    log = G.FaultLog()
+    G.copy_vec(t, mem, log, 0, addr["P"][0], addr["A"][0], 16, policy=G.SUPPRESS_ONLY)
+    assert log.count == 0 and log.first is None
+    with pytest.raises(ValueError):
+        G.copy_vec(t, mem, log, 0, addr["A"][0], addr["A"][0], 16, policy=7)
+
+
+# --- triad --------------------------------------------------------------------------
+def round_f32(x: Fraction) -> Fraction:
+    """Round a rational to the nearest binary32 value, ties to even (independent of numpy)."""
+    if x == 0:
+        return Fraction(0)
+    sgn = -1 if x < 0 else 1
+    a = abs(x)
+    e = a.numerator.bit_length() - a.denominator.bit_length()
+    if Fraction(2) ** e > a:
+        e -= 1
+    while Fraction(2) ** (e + 1) <= a:
+        e += 1
+    q = Fraction(2) ** (max(e, -126) - 23)
+    m = a / q
+    fl = m.numerator // m.denominator
+    rem = m - fl
+    if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and fl % 2 == 1):
+        fl += 1
+    r = fl * q
+    if r >= Fraction(2) ** 128:
+        return Fraction(sgn) * (Fraction(2) ** 200)   # stands for infinity
+    return sgn * r
+
+
+def _rand_f32(rng, n):
+    kind = rng.integers(0, 4, n)
+    mant = rng.uniform(-2, 2, n)
+    exp = np.where(kind == 0, rng.integers(-10, 10, n),
+                   np.where(kind == 1, rng.integers(-140, -120, n),
+                            np.where(kind == 2, rng.integers(20, 60, n), 0)))
+    return (mant * np.exp2(exp)).astype(np.float32)
+
+
+def test_triad_matches_exact_rational_rounding():
+    rng = np.random.default_rng(7)
+    n = 3000
+    b = _rand_f32(rng, n)
+    c = _rand_f32(rng, n)
+    for s in (np.float32(3.0), np.float32(-1.7), np.float32(1e-30), np.float32(0.0)):
+        t = RangeTable()
+        mem = Memory()
+        for k, arr in enumerate((np.zeros(n, np.float32), b, c)):
+            t.insert(BASE + k * (1 << 20), 4 * n, USER)
+            mem.add(BASE + k * (1 << 20), arr.view(np.uint8))
+        log = G.FaultLog()
+        G.triad_vec(t, mem, log, 0, BASE, BASE + (1 << 20), BASE + (2 << 20), float(s), n)
+        got = np.frombuffer(mem.read(BASE, 4 * n), dtype=np.float32)
+        assert log.count == 0
+        for i in range(n):
+            p = round_f32(Fraction(float(s)) * Fraction(float(c[i])))
+            r = round_f32(Fraction(float(b[i])) + p)
+            assert Fraction(float(got[i])) == r, (i, b[i], c[i], s, got[i])
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_triad_vec_matches_loop(seed):
+    t, mem, addr = scenario(seed)
+    rng = random.Random(seed)
+    ptrs = [p - (p % 4) for p in pointer_choices(addr)]
+    for trial in range(30):
+        a, b, c = rng.choice(ptrs), rng.choice(ptrs), rng.choice(ptrs)
+        n = rng.choice([0, 1, 5, 33, 150])
+        s = rng.choice([3.0, -0.5, 1.25])
+        if _overlap(a, 4 * n, b, 4 * n) or _overlap(a, 4 * n, c, 4 * n):
+            continue
+        m1, m2 = copy.deepcopy(mem), copy.deepcopy(mem)
+        l1, l2 = RecordingLog(), G.FaultLog()
+        G.triad_loop(t, m1, l1, trial, a, b, c, s, n)
+        G.triad_vec(t, m2, l2, trial, a, b, c, s, n)
+        _same(m1, m2, addr)
+        _logs_equal(l1, l2)
+        if l1.all:
+            assert min((x[0], x[1], x[2]) for x in l1.all) == l1.key()
+
+
+# --- gather / scatter ----------------------------------------------------------------
+def _write_idx(mem, addr, vals):
+    lo = addr["I"][0]
+    arr = np.array(vals, dtype=np.int64)
+    mem.write(lo, arr.tobytes())
+    return lo
+
+
+def hostile_indices(rng, rows, k):
+    choices = [0, 1, rows - 1, rows, rows + 1, -1, -2, rows * 3, -(1 << 62), (1 << 62),
+               -(1 << 63), (1 << 63) - 1]
+    return [rng.choice(choices + [rng.randrange(0, max(rows, 1))] * 6) for _ in range(k)]
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("w,D", [(4, 1), (4, 3), (8, 2)])
+def test_gather_vec_matches_loop(seed, w, D):
+    t, mem, addr = scenario(seed)
+    rng = random.Random(seed * 31 + D)
+    rb = w * D
+    for trial in range(20):
+        T = rng.choice([addr["A"][0], addr["A"][0] + rng.randrange(0, 40), addr["C"][0] + 4,
+                        addr["P"][0], BASE + 1500])
+        rows = max(1, (addr["A"][1] - T) // rb) if T < addr["A"][1] else 8
+        n = rng.choice([0, 1, 9, 40])
+        idx_ptr = _write_idx(mem, addr, hostile_indices(rng, rows, 64))
+        if rng.random() < 0.2:
+            idx_ptr = rng.choice([addr["I"][1] - 8 * 3, addr["P"][0]])
+        out = rng.choice([addr["C"][0], addr["C"][1] - rb * 5 - 2, addr["B"][0], addr["P"][0]])
+        if t.binding(out) != (0, 0) and t.binding(out) in (t.binding(T), t.binding(idx_ptr)):
+            continue      # output aliasing an input: order-dependent, unspecified
+        m1, m2 = copy.deepcopy(mem), copy.deepcopy(mem)
+        l1, l2 = RecordingLog(), G.FaultLog()
+        G.gather_loop(t, m1, l1, trial, out, T, rb, idx_ptr, n, w)
+        G.gather_vec(t, m2, l2, trial, out, T, rb, idx_ptr, n, w)
+        _same(m1, m2, addr)
+        _logs_equal(l1, l2)
+        assert l1.count == len(l1.all)
+        if l1.all:
+            assert min((x[0], x[1], x[2]) for x in l1.all) == l1.key()
+        assert m1.read(addr["P"][0], 128) == bytes([0xA5]) * 128
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("accumulate", [False, True])
+def test_scatter_vec_matches_loop(seed, accumulate):
+    t, mem, addr = scenario(seed)
+    rng = random.Random(seed + 100)
+    w, D = 4, 2
+    rb = w * D
+    # integer-valued float32 sources so that accumulation order cannot matter
+    for k in ("A", "C"):
+        lo, hi = addr[k]
+        vals = np.array([rng.randrange(-8, 9) for _ in range((hi - lo) // 4)], np.float32)
+        mem.write(lo, vals.tobytes() + bytes((hi - lo) % 4))
+    for trial in range(20):
+        dst = rng.choice([addr["A"][0], addr["A"][0] + 8, addr["P"][0], addr["C"][0]])
+        rows = 20
+        n = rng.choice([0, 1, 9, 30])
+        if accumulate:
+            iv = hostile_indices(rng, rows, 64)
+        else:
+            pool = list(range(rows)) + [rows + 5, -3, 1 << 40]
+            rng.shuffle(pool)
+            iv = pool[:min(n, len(pool))] + [0] * 64
+        idx_ptr = _write_idx(mem, addr, iv[:64])
+        src = rng.choice([addr["C"][0], addr["C"][1] - rb * 4, addr["P"][0], addr["B"][0]])
+        if t.binding(dst) != (0, 0) and t.binding(dst) in (t.binding(src), t.binding(idx_ptr)):
+            continue      # destination aliasing an input: order-dependent, unspecified
+        m1, m2 = copy.deepcopy(mem), copy.deepcopy(mem)
+        l1, l2 = RecordingLog(), G.FaultLog()
+        G.scatter_loop(t, m1, l1, trial, dst, rb, idx_ptr, src, n, w, accumulate)
+        G.scatter_vec(t, m2, l2, trial, dst, rb, idx_ptr, src, n, w, accumulate)
+        _same(m1, m2, addr)
+        _logs_equal(l1, l2)
+        if l1.all:
+            assert min((x[0], x[1], x[2]) for x in l1.all) == l1.key()
+        assert m1.read(addr["P"][0], 128) == bytes([0xA5]) * 128
+
+
+def test_gather_no_fault_is_take():
+    rng = np.random.default_rng(0)
+    rows, D, n = 300, 5, 1000
+    W = rng.standard_normal((rows, D)).astype(np.float32)
+    idx = rng.integers(0, rows, n).astype(np.int64)
+    t, mem = RangeTable(), Memory()
+    for k, arr in enumerate((W, idx, np.zeros((n, D), np.float32))):
+        t.insert(BASE + k * (1 << 20), arr.nbytes, USER)
+        mem.add(BASE + k * (1 << 20), arr.view(np.uint8).reshape(-1))
+    log = G.FaultLog()
+    G.gather_vec(t, mem, log, 0, BASE + (2 << 20), BASE, 4 * D, BASE + (1 << 20), n)
+    got = np.frombuffer(mem.read(BASE + (2 << 20), n * D * 4), np.float32).reshape(n, D)
+    assert np.array_equal(got, np.take(W, idx, axis=0)) and log.count == 0
+
+
+def test_scatter_add_unit_gradient_counts():
+    rng = np.random.default_rng(1)
+    rows, D, n = 50, 3, 2000
+    idx = rng.integers(0, rows, n).astype(np.int64)
+    idx[::97] = rows + 7          # out of bounds: dropped and logged
+    t, mem = RangeTable(), Memory()
+    for k, arr in enumerate((np.zeros((rows, D), np.float32), idx, np.ones((n, D), np.float32))):
+        t.insert(BASE + k * (1 << 20), arr.nbytes, USER)
+        mem.add(BASE + k * (1 << 20), arr.view(np.uint8).reshape(-1))
+    log = G.FaultLog()
+    G.scatter_vec(t, mem, log, 0, BASE, 4 * D, BASE + (1 << 20), BASE + (2 << 20), n,
+                  accumulate=True)
+    got = np.frombuffer(mem.read(BASE, rows * D * 4), np.float32).reshape(rows, D)
+    ok = idx < rows
+    want = np.bincount(idx[ok], minlength=rows).astype(np.float32)
+    assert np.array_equal(got, np.repeat(want[:, None], D, 1))
+    assert log.count == int((~ok).sum()) * D
+    assert log.first["elem"] == 0 and log.first["operand"] == 2
+    assert log.first["verdict"] in (V_UNMAPPED, V_CROSS_ALLOC, V_PROTECTED, V_STRADDLE)
+
+
+def test_fault_reason_codes():
+    t, mem, addr = scenario(0)
+    log = G.FaultLog()
+    # index past the table end into the adjacent allocation B -> CROSS_ALLOC, owner 1
+    idx_ptr = _write_idx(mem, addr, [512 // 4])
+    G.gather_vec(t, mem, log, 9, addr["C"][0], addr["A"][0], 4, idx_ptr, 1)
+    f = log.first
+    assert (f["verdict"], f["owner"], f["operand"], f["addr"]) == (V_CROSS_ALLOC, 1, 1,
+                                                                   addr["B"][0])
+    # into the protected canary -> PROTECTED with its owner id
+    log.clear()
+    idx_ptr = _write_idx(mem, addr, [(addr["P"][0] - addr["A"][0]) // 4])
+    G.gather_vec(t, mem, log, 10, addr["C"][0], addr["A"][0], 4, idx_ptr, 1)
+    assert log.first["verdict"] == V_PROTECTED and log.first["owner"] == 2
+    # into the hole -> UNMAPPED; below address zero -> UNMAPPED with owner -1
+    for iv in [(BASE + 1500 - addr["A"][0]) // 4, -(1 << 62)]:
+        log.clear()
+        idx_ptr = _write_idx(mem, addr, [iv])
+        G.gather_vec(t, mem, log, 11, addr["C"][0], addr["A"][0], 4, idx_ptr, 1)
+        assert log.first["verdict"] == V_UNMAPPED and log.first["owner"] == -1
+    # an access running over the allocation end -> STRADDLE on the own allocation
+    log.clear()
+    idx_ptr = _write_idx(mem, addr, [0])
+    G.gather_vec(t, mem, log, 12, addr["C"][0], addr["A"][1] - 2, 4, idx_ptr, 1)
+    assert log.first["verdict"] == V_STRADDLE and log.first["owner"] == 0
+    # suppressed loads read zero
+    assert mem.read(addr["C"][0], 4) == bytes(4)
+    assert ALLOW == 0
