@@ -1,0 +1,277 @@
+"""Benchmark of the range guard's hot path on one MI355X.
+
+Workload (large table, bandwidth-bound guarded kernels): a 65,536-range table (8,192 of them
+protected), 2^28 pointer queries with the 60/20/10/10 mix (inside USER / protected /
+straddling / unmapped), a guarded fp32 triad a = b + 3*c over three 1 GiB buffers, and a
+guarded gather of 2^26 int64 indices uniform over a 1 GiB fp32 table, 0.1% of them aimed at a
+protected range registered right after the table or at an unregistered hole after that.
+
+One step = validate all queries, run the guarded triad, run the guarded gather, then read and
+clear the fault log (the synchronization point where denials surface). Inputs are resident in
+HBM before timing starts. The unguarded twins of the triad and the gather are timed on the same
+inputs for the guarded/unguarded ratio. The CPU oracle is timed on a bounded sample.
+
+Prints one JSON line (see the "metric" and "roofline" keys).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+N_RANGES, N_PROT = 65536, 8192
+N_QUERIES = 1 << 28
+TRIAD_N = 1 << 28
+GATHER_ROWS = 1 << 28
+GATHER_N = 1 << 26
+PAD_BYTES = 64 << 10          # protected range right after the table, then a hole
+SEED = 1
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--queries-log2", type=int, default=28, help=argparse.SUPPRESS)
+    return p.parse_args()
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2606_06697_amd import guard as g
+    if not os.path.exists(g.LIB_PATH):
+        from paper_2606_06697_amd import _build
+        _build.build()
+    g.lib()
+    from synth import make_table, make_queries, uniform_f32, uniform_indices
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    nq = 1 << args.queries_log2
+
+    # ---------------- inputs (resident before timing) ----------------
+    tb = make_table(N_RANGES, N_PROT, SEED, first_hi=2**44)
+    vt = g.RangeTable(N_RANGES + 16)
+    vt.insert_many(tb.base, tb.size, tb.kind)
+    q = make_queries(tb, nq, SEED, device=dev)
+    verdict = torch.empty(nq, dtype=torch.uint8, device=dev)
+    owner = torch.empty(nq, dtype=torch.int32, device=dev)
+
+    a = torch.empty(TRIAD_N, dtype=torch.float32, device=dev)
+    b = uniform_f32(TRIAD_N, SEED, device=dev, stream=10)
+    c = uniform_f32(TRIAD_N, SEED, device=dev, stream=11)
+    a_ref = torch.empty_like(a)
+
+    gbuf = torch.empty(GATHER_ROWS * 4 + 2 * PAD_BYTES, dtype=torch.uint8, device=dev)
+    table = gbuf[:GATHER_ROWS * 4].view(torch.float32)
+    table.copy_(uniform_f32(GATHER_ROWS, SEED, device=dev, stream=12))
+    gbuf[GATHER_ROWS * 4:].fill_(0xA5)
+    prot_rows = (GATHER_ROWS, GATHER_ROWS + PAD_BYTES // 4)
+    hole_rows = (GATHER_ROWS + PAD_BYTES // 4, GATHER_ROWS + 2 * PAD_BYTES // 4)
+    idx = uniform_indices(GATHER_N, GATHER_ROWS, SEED, device=dev, bad_frac=0.001,
+                          bad_ranges=(prot_rows, hole_rows))
+    out = torch.empty(GATHER_N, dtype=torch.float32, device=dev)
+    out_ref = torch.empty_like(out)
+
+    # data table: the synthetic ranges plus the real buffers and the protected pad
+    dt = g.RangeTable(N_RANGES + 64)
+    dt.insert_many(tb.base, tb.size, tb.kind)
+    for t in (a, b, c, idx, out):
+        dt.insert_tensor(t)
+    dt.insert(table.data_ptr(), GATHER_ROWS * 4, g.KIND_USER)
+    dt.insert(table.data_ptr() + GATHER_ROWS * 4, PAD_BYTES, g.KIND_PROTECTED)
+    n_bad = int(((idx < 0) | (idx >= GATHER_ROWS)).sum())
+    torch.cuda.synchronize()
+
+    bytes_validate = nq * 21
+    bytes_triad = TRIAD_N * 12
+    bytes_gather = GATHER_N * 16
+    step_bytes = bytes_validate + bytes_triad + bytes_gather
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    t_kern = {"validate": [], "triad": [], "gather": []}
+
+    def step(timed):
+        if timed:
+            ev[0].record()
+        g.agile_validate_ptrs(vt.handle, q, nq, verdict, owner)
+        if timed:
+            ev[1].record()
+        g.agile_guarded_triad(dt.handle, a, b, c, 3.0, TRIAD_N)
+        if timed:
+            ev[2].record()
+        g.agile_guarded_gather(dt.handle, out, table, 4, idx, GATHER_N)
+        if timed:
+            ev[3].record()
+        rc, f = dt.fault_log(clear=True)       # synchronizes the stream
+        if timed:
+            t_kern["validate"].append(ev[0].elapsed_time(ev[1]))
+            t_kern["triad"].append(ev[1].elapsed_time(ev[2]))
+            t_kern["gather"].append(ev[2].elapsed_time(ev[3]))
+        return rc, f
+
+    for _ in range(args.warmup):
+        rc, f = step(False)
+    assert f["count"] == n_bad, (f["count"], n_bad)     # every hostile index denied once
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = elapsed * 1e3 / args.steps
+
+    # unguarded twins on the same inputs (the hostile indices stay inside the allocation)
+    ug = {"triad": [], "gather": []}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for name, fn in (("triad", lambda: g.agile_unguarded_triad(a_ref, b, c, 3.0, TRIAD_N)),
+                     ("gather", lambda: g.agile_unguarded_gather(out_ref, table, 4, idx,
+                                                                 GATHER_N))):
+        for _ in range(args.warmup):
+            fn()
+        for _ in range(args.steps):
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ug[name].append(e0.elapsed_time(e1))
+    torch.cuda.synchronize()
+    ok_triad = torch.equal(a.view(torch.int32), a_ref.view(torch.int32))
+    good = (idx >= 0) & (idx < GATHER_ROWS)
+    ok_gather = bool(torch.equal(out[good], out_ref[good])) and bool((out[~good] == 0).all())
+
+    def med(x):
+        return float(np.median(np.array(x)))
+
+    t_v, t_t, t_g = med(t_kern["validate"]), med(t_kern["triad"]), med(t_kern["gather"])
+    gbs = {"validate": bytes_validate / t_v / 1e6, "triad": bytes_triad / t_t / 1e6,
+           "gather": bytes_gather / t_g / 1e6}
+    ug_t, ug_g = med(ug["triad"]), med(ug["gather"])
+    ugbs = {"triad": bytes_triad / ug_t / 1e6, "gather": bytes_gather / ug_g / 1e6}
+    dominant = max(("validate", t_v), ("triad", t_t), ("gather", t_g), key=lambda x: x[1])[0]
+    avg_ms = {"validate": float(np.mean(t_kern["validate"])),
+              "triad": float(np.mean(t_kern["triad"])),
+              "gather": float(np.mean(t_kern["gather"]))}
+    per_launch = {"validate": bytes_validate, "triad": bytes_triad, "gather": bytes_gather}
+    achieved = per_launch[dominant] / avg_ms[dominant] / 1e6
+    value = step_bytes / (ms_step / 1e3) / 1e9
+
+    result = {
+        "metric": "guarded vs unguarded HBM GB/s (% overhead); ptr validations/s; "
+                  "p50/p99 latency",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "large table + bandwidth-bound guarded kernels: 65536 ranges "
+                               "(8192 protected), 2^28 validation queries, guarded fp32 triad "
+                               "3x1 GiB, guarded gather 2^26 int64 idx over 1 GiB fp32 "
+                               "(0.1% hostile)",
+                   "queries": nq, "ranges": N_RANGES, "triad_elems": TRIAD_N,
+                   "gather_idx": GATHER_N, "gather_rows": GATHER_ROWS},
+        "validations_per_s": round(nq / (t_v / 1e3), 1),
+        "kernel_ms": {"validate": round(t_v, 4), "triad": round(t_t, 4),
+                      "gather": round(t_g, 4), "triad_unguarded": round(ug_t, 4),
+                      "gather_unguarded": round(ug_g, 4)},
+        "guarded_gbps": {k: round(v, 1) for k, v in gbs.items()},
+        "unguarded_gbps": {k: round(v, 1) for k, v in ugbs.items()},
+        "guarded_over_unguarded": {k: round(gbs[k] / ugbs[k], 4) for k in ugbs},
+        "overhead_pct": {k: round(100.0 * (ugbs[k] / gbs[k] - 1.0), 2) for k in ugbs},
+        "unguarded_frac_of_peak": {k: round(v / PEAK_HBM_GBS, 4) for k, v in ugbs.items()},
+        "faults_per_step": n_bad,
+        "twin_results_equal": {"triad": ok_triad, "gather": ok_gather},
+        "latency_p50_ms": None,
+        "latency_p99_ms": None,
+        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1),
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "bytes_per_launch": per_launch[dominant]},
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(tb, step_bytes, nq)
+    print(json.dumps(result), flush=True)
+
+
+def cpu_baseline(tb, step_bytes, nq):
+    """Time the oracle (as it stands) on a bounded sample of the same workload, single thread,
+    and scale each part to its full size."""
+    import numpy as np
+    import torch
+
+    from oracle.table import RangeTable as OT
+    from oracle.memory import Memory
+    from oracle import guarded as G
+    from synth import make_queries, uniform_f32, uniform_indices
+
+    ot = OT()
+    for bb, s, k in zip(tb.base.tolist(), tb.size.tolist(), tb.kind.tolist()):
+        ot.insert(bb, s, k)
+    nsv = 1 << 23
+    qs = make_queries(tb, nsv, SEED + 100).numpy().view(np.uint64)
+    t0 = time.perf_counter()
+    ot.verdict_many(qs[:, 0], qs[:, 1])
+    tv = time.perf_counter() - t0
+
+    nst = 1 << 22
+    base = 1 << 40
+    mt, tt = Memory(), OT()
+    for k, arr in enumerate((np.zeros(nst, np.float32), uniform_f32(nst, 5).numpy(),
+                             uniform_f32(nst, 6).numpy())):
+        tt.insert(base + k * (1 << 30), 4 * nst, 0)
+        mt.add(base + k * (1 << 30), arr.view(np.uint8))
+    t0 = time.perf_counter()
+    G.triad_vec(tt, mt, G.FaultLog(), 0, base, base + (1 << 30), base + (2 << 30), 3.0, nst)
+    ttr = time.perf_counter() - t0
+
+    nsg, rows = 1 << 18, 1 << 22
+    mg, tg = Memory(), OT()
+    idx = uniform_indices(nsg, rows, 7, bad_frac=0.001,
+                          bad_ranges=((rows, rows + 16384), (rows + 16384, rows + 32768))).numpy()
+    tg.insert(base, rows * 4, 0)
+    tg.insert(base + rows * 4, PAD_BYTES, 1)
+    mg.add(base, uniform_f32(rows, 8).numpy().view(np.uint8))
+    tg.insert(base + (1 << 30), nsg * 8, 0)
+    mg.add(base + (1 << 30), idx.view(np.uint8))
+    tg.insert(base + (2 << 30), nsg * 4, 0)
+    mg.add(base + (2 << 30), np.zeros(nsg * 4, np.uint8))
+    t0 = time.perf_counter()
+    G.gather_vec(tg, mg, G.FaultLog(), 0, base + (2 << 30), base, 4, base + (1 << 30), nsg)
+    tgt = time.perf_counter() - t0
+
+    cpu_step = tv * nq / nsv + ttr * TRIAD_N / nst + tgt * GATHER_N / nsg
+    return {"value": round(step_bytes / cpu_step / 1e9, 4), "unit": "GB/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"validate {nsv} queries on the same 65536-range table ({tv:.2f} s), "
+                      f"triad {nst} elems ({ttr:.2f} s), gather {nsg} idx over {rows} rows "
+                      f"({tgt:.2f} s); each scaled to its full size; host "
+                      f"{platform.processor() or platform.machine()}, {os.cpu_count()} cpus "
+                      "visible, numpy single-threaded",
+            "validations_per_s": round(nsv / tv, 1)}
+
+
+if __name__ == "__main__":
+    main()

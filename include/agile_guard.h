@@ -1,0 +1,213 @@
+/*
+ * agile_guard.h - C ABI of the MI355X (gfx950) range guard library (libagile_guard.so).
+ *
+ * Implements the data-parallel part of the protected GPU memory model of AgileOS
+ * (arXiv 2606.06697): an allocation table that separates user allocations from protected
+ * module and MMIO ranges (Section IV-E, Table I; Section V-A records each allocation's base
+ * and live size), batched API-time pointer validation (Section IV-E, V-C), and guarded
+ * kernels whose every global access is checked before it happens, with the paper's
+ * "poison" (record, fail later) and "sink" (redirect to a quarantine page) policies
+ * (Section V-E).
+ *
+ * Conventions for every entry point
+ *  - Return value: AGILE_OK (0) or a negative AGILE_E* code; nothing is thrown across the
+ *    ABI. Invalid arguments are rejected before any device work is queued (unsupported
+ *    requests fail closed, Section IV-C). Out-parameters are written only on AGILE_OK,
+ *    except agile_fault_log_read, which also fills its record when it returns
+ *    AGILE_EFAULTED.
+ *  - Ownership: the library owns each table handle, its device image and its fault log.
+ *    The caller owns every data, query and output buffer (device pointers) and every
+ *    stream; the library never frees caller memory.
+ *  - Streams: `stream` is a hipStream_t (NULL = the legacy default stream). Device work is
+ *    queued asynchronously on it. Table mutations take effect for work queued after them
+ *    (the device image is refreshed lazily, in stream order, by the next launch).
+ *  - Threading: one handle must not be used from two host threads at once, and guarded
+ *    calls on one handle that run concurrently on different streams race on its fault
+ *    scratch; order them (one stream, or events).
+ *  - Guard denials are not errors: validation reports them as verdicts, guarded kernels
+ *    suppress them (loads read zero bits, stores are dropped) and count them in the log.
+ *  - Overlap: a guarded kernel's output must not alias its inputs except an elementwise
+ *    output identical to an input (a == b in the triad); otherwise results are unspecified
+ *    (the guard still never writes outside the output's own allocation).
+ */
+#ifndef AGILE_GUARD_H
+#define AGILE_GUARD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct agile_rt agile_rt; /* opaque, library-owned range-table handle */
+
+enum {
+    AGILE_OK = 0,
+    AGILE_EINVAL = -1,    /* null handle/pointer, unknown enum value, bad size or alignment */
+    AGILE_ENOMEM = -2,    /* device or pinned host allocation failed */
+    AGILE_EOVERLAP = -3,  /* inserted range intersects an existing range */
+    AGILE_ENOENT = -4,    /* unknown or already removed range id */
+    AGILE_ENOSPC = -5,    /* table at capacity, or the id space (2^30 ids) is used up */
+    AGILE_EDEVICE = -6,   /* a HIP runtime call or kernel launch failed */
+    AGILE_EFAULTED = -7   /* fault log is non-empty ("poison" surfaces here) */
+};
+
+/* Range kinds (Table I): user allocations, protected module/service memory, MMIO. */
+enum { AGILE_KIND_USER = 0, AGILE_KIND_PROTECTED = 1, AGILE_KIND_MMIO = 2 };
+
+/* Verdicts. The owner of the first byte decides: no owner -> UNMAPPED; a protected or
+ * MMIO owner -> PROTECTED; a USER owner -> ALLOW if max(len,1) <= end - addr, else
+ * STRADDLE (the byte range must stay inside one live allocation, Section V-C).
+ * CROSS_ALLOC only appears as a fault reason: a guarded access that lands in a different
+ * user allocation than its argument's. */
+enum {
+    AGILE_ALLOW = 0,
+    AGILE_V_PROTECTED = 1,
+    AGILE_V_STRADDLE = 2,
+    AGILE_V_UNMAPPED = 3,
+    AGILE_V_CROSS_ALLOC = 4
+};
+
+/* Guard policies (Section V-E): SUPPRESS_LOG = sink to a zero page + poison record;
+ * SUPPRESS_ONLY = sink without a record. */
+enum { AGILE_POLICY_SUPPRESS_LOG = 0, AGILE_POLICY_SUPPRESS_ONLY = 1 };
+
+/* Guarded operations, as recorded in a fault record. */
+enum {
+    AGILE_OP_COPY = 1,
+    AGILE_OP_TRIAD = 2,
+    AGILE_OP_GATHER = 3,
+    AGILE_OP_SCATTER = 4,
+    AGILE_OP_SCATTER_ADD = 5
+};
+
+/* Element types of gather/scatter (element width 4 or 8 bytes). */
+enum { AGILE_DTYPE_F32 = 0, AGILE_DTYPE_F64 = 1 };
+
+/* One pointer query: 16 bytes, array-of-structs in device memory. */
+typedef struct {
+    uint64_t addr;
+    uint64_t len;
+} agile_ptr;
+
+/* Fault log (56 bytes). `count` is the exact number of denied accesses since the last
+ * clear (one per denied element access of its operand's width). The record describes the
+ * denial with the smallest key (first_seq, first_elem, first_operand): first_seq numbers
+ * the handle's guarded calls in call order from 0, first_elem is the flat element index
+ * (byte for copy, element for triad, row*D+col for gather/scatter, row*D for an index
+ * load), first_operand the operand's position in its op's access order (copy: src 0,
+ * dst 1; triad: b 0, c 1, a 2; gather: idx 0, table 1, out 2; scatter: idx 0, src 1,
+ * dst 2). first_addr is the access address mod 2^64, first_verdict the classification
+ * of [addr, addr+width) with ALLOW reported as CROSS_ALLOC (UNMAPPED if the exact
+ * address lies outside [0, 2^64)), first_owner that range's id or -1.
+ * first_seq == UINT64_MAX means no record. */
+typedef struct {
+    uint64_t count;
+    uint64_t first_seq;
+    uint64_t first_elem;
+    uint64_t first_addr;
+    uint32_t first_width;
+    uint32_t first_op;
+    uint32_t first_operand;
+    uint32_t first_verdict;
+    int32_t first_owner;
+    uint32_t reserved;
+} agile_fault;
+
+/* ---- range table (the allocation table of Section V-A / V-C) --------------------- */
+
+/* Create an empty table for up to `capacity` ranges (1 <= capacity <= 2^26) on HIP device
+ * `device`; allocates its device image, fault log and pinned staging. *out receives the
+ * handle. Errors: EINVAL, ENOMEM, EDEVICE. */
+int agile_rt_create(agile_rt** out, uint32_t capacity, int device);
+
+/* Destroy a handle after all work queued with it has completed (the call synchronizes the
+ * handle's device before freeing). Removing a client's state revokes its ranges (Section
+ * IV-D, lifetime and revocation). NULL is accepted. */
+int agile_rt_destroy(agile_rt* rt);
+
+/* Insert the half-open range [base, base+size) of `kind`. Requires size >= 1 and
+ * base + size <= 2^64 - 1. Adjacent ranges are legal; any intersection gives EOVERLAP.
+ * *out_id (may be NULL) receives the new stable id: 0, 1, 2, ... in insertion order,
+ * never reused. Errors: EINVAL, EOVERLAP, ENOSPC. */
+int agile_rt_insert(agile_rt* rt, uint64_t base, uint64_t size, uint32_t kind,
+                    int32_t* out_id);
+
+/* Insert n ranges (host arrays) as one all-or-nothing batch, in array order; ids are
+ * assigned in that order. out_ids (may be NULL) receives n ids. */
+int agile_rt_insert_many(agile_rt* rt, const uint64_t* base, const uint64_t* size,
+                         const uint8_t* kind, uint32_t n, int32_t* out_ids);
+
+/* Remove range `id` (a freed allocation): its bytes become a hole, so later validation
+ * reports UNMAPPED there (freed allocations are rejected, Section IV-E, V-C).
+ * Errors: EINVAL, ENOENT. */
+int agile_rt_remove(agile_rt* rt, int32_t id);
+
+/* Number of live ranges. */
+int agile_rt_count(const agile_rt* rt, uint32_t* out_n);
+
+/* Upload pending table changes now on `stream` (optional: every launch does it lazily). */
+int agile_rt_sync(agile_rt* rt, void* stream);
+
+/* ---- batched API-time pointer validation (Section IV-E, V-C) ----------------------- */
+
+/* Classify n queries d_q[i] = (addr, len) against the table: d_verdict[i] (uint8, AGILE_ALLOW
+ * .. AGILE_V_UNMAPPED) and d_owner[i] (int32 range id, -1 when unmapped). All three arrays
+ * are caller-owned device memory of n elements; d_q must be 16-byte aligned. n == 0 is a
+ * no-op. Errors: EINVAL, EDEVICE. */
+int agile_validate_ptrs(agile_rt* rt, const agile_ptr* d_q, uint64_t n, uint8_t* d_verdict,
+                        int32_t* d_owner, void* stream);
+
+/* ---- guarded kernels (kernel memory guard, Section V-E) ----------------------------
+ * Each pointer argument is bound once, on the device, to the USER range that contains
+ * it (empty if none); every element access is then allowed only if it lies wholly inside
+ * its argument's range. Each call takes the next sequence number of the handle. */
+
+/* dst[k] = src[k] for bytes k < nbytes. Denied src bytes read 0, denied dst bytes are left
+ * unchanged. Any alignment; 16-byte-aligned pointers take the vector path. */
+int agile_guarded_copy(agile_rt* rt, void* d_dst, const void* d_src, uint64_t nbytes,
+                       int policy, void* stream);
+
+/* a[i] = b[i] + s*c[i] for i < n, fp32, rounded twice (no fused multiply-add), denormals
+ * kept. 4-byte-aligned pointers required (EINVAL otherwise). */
+int agile_guarded_triad(agile_rt* rt, float* d_a, const float* d_b, const float* d_c, float s,
+                        uint64_t n, int policy, void* stream);
+
+/* out[i, :] = table[idx[i], :] for i < n, rows of row_bytes bytes (a multiple of the
+ * element width of dtype), the row address table + idx[i]*row_bytes computed exactly (an
+ * index never wraps around the address space). idx is int64. Requires n*row_bytes/width
+ * < 2^62. Pointers must be aligned to the element width. */
+int agile_guarded_gather(agile_rt* rt, void* d_out, const void* d_table, uint64_t row_bytes,
+                         const int64_t* d_idx, uint64_t n, int dtype, int policy,
+                         void* stream);
+
+/* dst[idx[i], :] = src[i, :] (accumulate == 0; with duplicate indices one writer wins) or
+ * dst[idx[i], :] += src[i, :] (accumulate == 1, atomic adds in unspecified order). */
+int agile_guarded_scatter(agile_rt* rt, void* d_dst, uint64_t row_bytes, const int64_t* d_idx,
+                          const void* d_src, uint64_t n, int dtype, int accumulate, int policy,
+                          void* stream);
+
+/* Read the fault log (queues a device-to-host copy on `stream` and synchronizes it).
+ * *out receives the log; clear != 0 then resets it on `stream`. Returns AGILE_EFAULTED when
+ * the log holds at least one denial (the paper's "poison" policy reports a violation at a
+ * later synchronization boundary, Section V-E), AGILE_OK when it is empty. */
+int agile_fault_log_read(agile_rt* rt, agile_fault* out, int clear, void* stream);
+
+/* ---- unguarded twins (same kernels with the guard compiled out; measurement only) ---- */
+int agile_unguarded_copy(void* d_dst, const void* d_src, uint64_t nbytes, void* stream);
+int agile_unguarded_triad(float* d_a, const float* d_b, const float* d_c, float s, uint64_t n,
+                          void* stream);
+int agile_unguarded_gather(void* d_out, const void* d_table, uint64_t row_bytes,
+                           const int64_t* d_idx, uint64_t n, int dtype, void* stream);
+int agile_unguarded_scatter(void* d_dst, uint64_t row_bytes, const int64_t* d_idx,
+                            const void* d_src, uint64_t n, int dtype, int accumulate,
+                            void* stream);
+
+/* Static text for a status code. */
+const char* agile_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AGILE_GUARD_H */

@@ -1,0 +1,206 @@
+// Device-side data layout and helpers shared by the guard kernels (gfx950, wave64).
+//
+// Table image (built on the host from the sorted range list, uploaded in stream order):
+//   split64[b]  u64  base of the first range of bucket b (buckets hold 2 consecutive
+//                    ranges in address order), nb = ceil(n/2) entries
+//   split32[b]  u32  (split64[b] - gmin) >> shift, present when every bucket base is a
+//                    multiple of 2^shift above gmin and the keys fit 32 bits; a query key
+//                    (addr - gmin) >> shift then orders exactly like the address
+//   rec[b]      32 B {base of the 2nd range (U64 max if none), end of 1st, end of 2nd,
+//                    meta of 1st, meta of 2nd}, meta = id << 2 | kind
+// A lookup finds the last bucket whose base is <= addr, then reads one 32-byte record to
+// pick the range inside the bucket and to get its end, id and kind.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "guard_arith.h"
+
+namespace agile {
+
+constexpr uint32_t KIND_USER = 0;
+constexpr uint8_t V_ALLOW = 0, V_PROTECTED = 1, V_STRADDLE = 2, V_UNMAPPED = 3,
+                  V_CROSS_ALLOC = 4;
+constexpr uint64_t U64MAX = ~0ull;
+
+struct alignas(32) PairRec {
+    uint64_t base1;
+    uint64_t end0;
+    uint64_t end1;
+    uint32_t meta0;
+    uint32_t meta1;
+};
+static_assert(sizeof(PairRec) == 32, "PairRec is one 32-byte sector");
+
+struct DevTable {
+    const uint64_t* split64;
+    const uint32_t* split32;
+    const PairRec* rec;
+    uint64_t gmin;
+    uint32_t nb;          // number of buckets (0 for an empty table)
+    uint32_t shift;
+    uint32_t compressed;  // split32 valid
+    uint32_t pad;
+};
+
+// Device copy of the public fault log (same field order as agile_fault) + per-launch scratch.
+struct DevLog {
+    unsigned long long count;
+    unsigned long long first_seq;
+    unsigned long long first_elem;
+    unsigned long long first_addr;
+    uint32_t first_width;
+    uint32_t first_op;
+    uint32_t first_operand;
+    uint32_t first_verdict;
+    int32_t first_owner;
+    uint32_t reserved;
+    // scratch used inside one guarded launch, returned to its idle state by the launch's
+    // last workgroup
+    unsigned long long s_minkey;   // min over (elem << 2 | operand) of this launch's denials
+    unsigned long long s_count;    // denials of this launch
+    unsigned int s_done;           // workgroups finished
+    unsigned int s_pad;
+};
+
+// Classification of `a` inside bucket b (split64[b] <= a is known): verdict + owner for a
+// length-L query (L >= 1).
+__device__ __forceinline__ void classify_in_bucket(const PairRec& r, uint64_t a, uint64_t L,
+                                                   uint8_t& v, int32_t& owner) {
+    const bool second = r.base1 <= a;
+    const uint64_t end = second ? r.end1 : r.end0;
+    const uint32_t meta = second ? r.meta1 : r.meta0;
+    if (a >= end) {
+        v = V_UNMAPPED;
+        owner = -1;
+        return;
+    }
+    owner = (int32_t)(meta >> 2);
+    if ((meta & 3u) != KIND_USER) {
+        v = V_PROTECTED;
+    } else {
+        v = (L <= end - a) ? V_ALLOW : V_STRADDLE;
+    }
+}
+
+__device__ __forceinline__ PairRec load_rec(const PairRec* p) {
+    const ulonglong2* q = reinterpret_cast<const ulonglong2*>(p);
+    ulonglong2 x = q[0];
+    ulonglong2 y = q[1];
+    PairRec r;
+    r.base1 = x.x;
+    r.end0 = x.y;
+    r.end1 = y.x;
+    r.meta0 = (uint32_t)y.y;
+    r.meta1 = (uint32_t)(y.y >> 32);
+    return r;
+}
+
+// Last bucket with split64[b] <= a, or -1. One lane, binary search over global memory
+// (used for single lookups in fault records).
+__device__ inline int64_t bucket_search_lane(const DevTable& t, uint64_t a) {
+    if (t.nb == 0 || t.split64[0] > a) return -1;
+    uint32_t base = 0, len = t.nb;
+    while (len > 1) {
+        uint32_t half = len >> 1;
+        base = (t.split64[base + half] <= a) ? base + half : base;
+        len -= half;
+    }
+    return base;
+}
+
+__device__ inline void verdict_lane(const DevTable& t, uint64_t a, uint64_t len, uint8_t& v,
+                                    int32_t& owner) {
+    int64_t b = bucket_search_lane(t, a);
+    if (b < 0) {
+        v = V_UNMAPPED;
+        owner = -1;
+        return;
+    }
+    classify_in_bucket(load_rec(t.rec + b), a, len < 1 ? 1 : len, v, owner);
+}
+
+// Wave-cooperative search for a wave-uniform address: each step compares 64 evenly spaced
+// splitters at once (ballot + popcount), shrinking the candidate range 64x per step.
+__device__ inline int64_t bucket_search_wave(const DevTable& t, uint64_t a) {
+    const uint32_t lane = __lane_id();
+    uint32_t lo = 0, cnt = t.nb;
+    if (cnt == 0) return -1;
+    while (true) {
+        uint32_t step = cnt <= 64 ? 1u : (cnt + 63u) / 64u;
+        uint32_t off = lane * step;
+        bool ok = off < cnt && t.split64[lo + off] <= a;
+        uint32_t c = (uint32_t)__popcll(__ballot(ok));
+        if (c == 0) return lo == 0 ? -1 : (int64_t)lo - 1;  // lo>0 cannot happen: split[lo] <= a
+        lo += (c - 1) * step;
+        if (step == 1) return lo;
+        uint32_t rest = cnt - (c - 1) * step;
+        cnt = rest < step ? rest : step;
+    }
+}
+
+// Move a wave-uniform 64-bit value into scalar registers (readfirstlane works on 32-bit
+// halves and returns int: widen through uint32_t so no sign bits leak into the high half).
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Binding of a kernel pointer argument (wave-uniform): the USER range containing p.
+__device__ inline Bind bind_wave(const DevTable& t, uint64_t p) {
+    Bind r{0, 0};
+    int64_t b = bucket_search_wave(t, p);
+    if (b < 0) return r;
+    PairRec rec = load_rec(t.rec + b);
+    const bool second = rec.base1 <= p;
+    const uint64_t end = second ? rec.end1 : rec.end0;
+    const uint32_t meta = second ? rec.meta1 : rec.meta0;
+    if (p < end && (meta & 3u) == KIND_USER) {
+        r.lo = second ? rec.base1 : t.split64[b];
+        r.hi = end;
+    }
+    r.lo = uniform_u64(r.lo);
+    r.hi = uniform_u64(r.hi);
+    return r;
+}
+
+// Reason recorded for a denied access at address a (already known to lie in [0, 2^64)).
+__device__ inline void reason_lane(const DevTable& t, uint64_t a, uint32_t w, uint32_t& v,
+                                   int32_t& owner) {
+    uint8_t vv;
+    verdict_lane(t, a, w, vv, owner);
+    v = (vv == V_ALLOW) ? V_CROSS_ALLOC : vv;
+}
+
+// Write the first-fault record if the log has none yet (launches of one handle are ordered,
+// so an earlier launch's record always wins).
+__device__ inline void log_record(DevLog* log, unsigned long long seq, unsigned long long elem,
+                                  uint32_t operand, uint64_t addr, uint32_t width, uint32_t op,
+                                  uint32_t verdict, int32_t owner) {
+    if (log->first_seq != ~0ull) return;
+    log->first_elem = elem;
+    log->first_addr = addr;
+    log->first_width = width;
+    log->first_op = op;
+    log->first_operand = operand;
+    log->first_verdict = verdict;
+    log->first_owner = owner;
+    __threadfence();
+    log->first_seq = seq;
+}
+
+// Wave reductions (wave64).
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x) {
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long x) {
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned long long y = __shfl_xor(x, o, 64);
+        x = y < x ? y : x;
+    }
+    return x;
+}
+
+}  // namespace agile

@@ -1,0 +1,523 @@
+// Host runtime of libagile_guard.so: the C ABI declared in include/agile_guard.h.
+//
+// A handle keeps the allocation table (AgileOS Section V-A/V-C: base and live size of every
+// range, plus its kind from the Table I layout) as a sorted host mirror with stable ids, and a
+// device image rebuilt from it when the table changed. The image is uploaded lazily by the next
+// launch, on that launch's stream, after every other stream that used the handle has been made
+// to wait for its earlier work; the pinned staging buffer is reused only after its previous
+// upload completed. Guarded calls take consecutive sequence numbers (the first-fault order).
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/agile_guard.h"
+#include "launch.h"
+
+using namespace agile;
+
+namespace {
+
+struct Entry {
+    uint64_t base, end;
+    int32_t id;
+    uint8_t kind;
+};
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) return;
+        ok = prev == dev || hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+constexpr uint32_t MAX_CAPACITY = 1u << 26;
+constexpr int32_t MAX_ID = (1 << 30) - 1;
+
+}  // namespace
+
+struct agile_rt {
+    int device = 0;
+    uint32_t capacity = 0;
+    uint32_t cap_nb = 0;
+    std::vector<Entry> entries;                 // sorted by base
+    std::unordered_map<int32_t, uint64_t> by_id;  // id -> base
+    int32_t next_id = 0;
+    bool dirty = true;
+    unsigned long long seq = 0;
+    DevInfo info{};
+    size_t lds_budget = 0;
+    // device image
+    void* dmem = nullptr;
+    uint64_t* d_split64 = nullptr;
+    uint32_t* d_split32 = nullptr;
+    PairRec* d_rec = nullptr;
+    DevLog* d_log = nullptr;
+    DevTable tab{};
+    // pinned staging
+    void* hstage = nullptr;
+    size_t stage_bytes = 0;
+    agile_fault* hlog = nullptr;
+    hipEvent_t upload_done = nullptr;
+    bool upload_pending = false;
+    std::vector<hipStream_t> streams_used;
+};
+
+static size_t image_bytes(uint32_t cap_nb) {
+    return (size_t)cap_nb * 8 + (size_t)cap_nb * 4 + 64 + (size_t)cap_nb * sizeof(PairRec);
+}
+
+static void note_stream(agile_rt* rt, hipStream_t s) {
+    for (hipStream_t x : rt->streams_used)
+        if (x == s) return;
+    rt->streams_used.push_back(s);
+}
+
+// Build the image into the staging buffer and queue its upload on stream s.
+static int upload(agile_rt* rt, hipStream_t s) {
+    if (!rt->dirty) return AGILE_OK;
+    if (rt->upload_pending) {
+        if (hipEventSynchronize(rt->upload_done) != hipSuccess) return AGILE_EDEVICE;
+        rt->upload_pending = false;
+    }
+    const uint32_t n = (uint32_t)rt->entries.size();
+    const uint32_t nb = (n + 1) / 2;
+    uint8_t* h = static_cast<uint8_t*>(rt->hstage);
+    uint64_t* s64 = reinterpret_cast<uint64_t*>(h);
+    uint32_t* s32 = reinterpret_cast<uint32_t*>(h + (size_t)rt->cap_nb * 8);
+    PairRec* rec = reinterpret_cast<PairRec*>(h + (size_t)rt->cap_nb * 12 + 64 -
+                                              (((size_t)rt->cap_nb * 12) % 64));
+    const auto& E = rt->entries;
+    for (uint32_t b = 0; b < nb; ++b) {
+        const Entry& e0 = E[2 * b];
+        s64[b] = e0.base;
+        PairRec r;
+        r.end0 = e0.end;
+        r.meta0 = ((uint32_t)e0.id << 2) | e0.kind;
+        if (2 * b + 1 < n) {
+            const Entry& e1 = E[2 * b + 1];
+            r.base1 = e1.base;
+            r.end1 = e1.end;
+            r.meta1 = ((uint32_t)e1.id << 2) | e1.kind;
+        } else {
+            r.base1 = U64MAX;
+            r.end1 = 0;
+            r.meta1 = 0;
+        }
+        rec[b] = r;
+    }
+    DevTable t{};
+    t.split64 = rt->d_split64;
+    t.split32 = rt->d_split32;
+    t.rec = rt->d_rec;
+    t.nb = nb;
+    t.compressed = 0;
+    if (nb > 0) {
+        const uint64_t gmin = s64[0];
+        const uint64_t span = s64[nb - 1] - gmin;
+        uint32_t sh = 0;
+        while (sh < 63 && (span >> sh) > 0xFFFFFFFEull) ++sh;
+        const uint64_t mask = (sh == 0) ? 0 : ((1ull << sh) - 1);
+        bool ok = (span >> sh) <= 0xFFFFFFFEull;
+        for (uint32_t b = 0; ok && b < nb; ++b) ok = ((s64[b] - gmin) & mask) == 0;
+        if (ok) {
+            for (uint32_t b = 0; b < nb; ++b) s32[b] = (uint32_t)((s64[b] - gmin) >> sh);
+            t.compressed = 1;
+            t.gmin = gmin;
+            t.shift = sh;
+        }
+    }
+    // make every other stream that used the handle finish with the old image first
+    for (hipStream_t o : rt->streams_used) {
+        if (o == s) continue;
+        hipEvent_t ev;
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return AGILE_EDEVICE;
+        if (hipEventRecord(ev, o) != hipSuccess || hipStreamWaitEvent(s, ev, 0) != hipSuccess) {
+            (void)hipEventDestroy(ev);
+            return AGILE_EDEVICE;
+        }
+        (void)hipEventDestroy(ev);
+    }
+    rt->streams_used.clear();
+    if (nb > 0) {
+        if (hipMemcpyAsync(rt->d_split64, s64, (size_t)nb * 8, hipMemcpyHostToDevice, s) != hipSuccess)
+            return AGILE_EDEVICE;
+        if (t.compressed &&
+            hipMemcpyAsync(rt->d_split32, s32, (size_t)nb * 4, hipMemcpyHostToDevice, s) != hipSuccess)
+            return AGILE_EDEVICE;
+        if (hipMemcpyAsync(rt->d_rec, rec, (size_t)nb * sizeof(PairRec), hipMemcpyHostToDevice, s) !=
+            hipSuccess)
+            return AGILE_EDEVICE;
+        if (hipEventRecord(rt->upload_done, s) != hipSuccess) return AGILE_EDEVICE;
+        rt->upload_pending = true;
+    }
+    rt->tab = t;
+    rt->dirty = false;
+    return AGILE_OK;
+}
+
+static int prepare(agile_rt* rt, hipStream_t s) {
+    int rc = upload(rt, s);
+    if (rc != AGILE_OK) return rc;
+    note_stream(rt, s);
+    return AGILE_OK;
+}
+
+extern "C" {
+
+const char* agile_strerror(int code) {
+    switch (code) {
+        case AGILE_OK: return "ok";
+        case AGILE_EINVAL: return "invalid argument";
+        case AGILE_ENOMEM: return "out of memory";
+        case AGILE_EOVERLAP: return "range overlaps an existing range";
+        case AGILE_ENOENT: return "no such range id";
+        case AGILE_ENOSPC: return "range table full";
+        case AGILE_EDEVICE: return "HIP runtime error";
+        case AGILE_EFAULTED: return "guarded access denied (fault log not empty)";
+        default: return "unknown status";
+    }
+}
+
+int agile_rt_create(agile_rt** out, uint32_t capacity, int device) {
+    if (!out || capacity < 1 || capacity > MAX_CAPACITY) return AGILE_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess) return AGILE_EDEVICE;
+    if (device < 0 || device >= ndev) return AGILE_EINVAL;
+    DeviceGuard dg(device);
+    if (!dg.ok) return AGILE_EDEVICE;
+    agile_rt* rt = new (std::nothrow) agile_rt();
+    if (!rt) return AGILE_ENOMEM;
+    rt->device = device;
+    rt->capacity = capacity;
+    rt->cap_nb = (capacity + 1) / 2;
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, device) != hipSuccess) {
+        delete rt;
+        return AGILE_EDEVICE;
+    }
+    rt->info.num_cu = p.multiProcessorCount;
+    rt->info.lds_per_block = p.sharedMemPerBlock;
+    rt->info.lds_per_cu = p.maxSharedMemoryPerMultiProcessor;
+    rt->lds_budget = 128 * 1024;
+    if (const char* e = std::getenv("AGILE_LDS_BUDGET")) {
+        long v = std::strtol(e, nullptr, 10);
+        if (v >= 1024) rt->lds_budget = (size_t)v;
+    }
+    rt->stage_bytes = image_bytes(rt->cap_nb);
+    const size_t dev_bytes = rt->stage_bytes + 256 + sizeof(DevLog);
+    if (hipMalloc(&rt->dmem, dev_bytes) != hipSuccess) {
+        delete rt;
+        return AGILE_ENOMEM;
+    }
+    uint8_t* d = static_cast<uint8_t*>(rt->dmem);
+    rt->d_split64 = reinterpret_cast<uint64_t*>(d);
+    rt->d_split32 = reinterpret_cast<uint32_t*>(d + (size_t)rt->cap_nb * 8);
+    rt->d_rec = reinterpret_cast<PairRec*>(d + (size_t)rt->cap_nb * 12 + 64 -
+                                           (((size_t)rt->cap_nb * 12) % 64));
+    rt->d_log = reinterpret_cast<DevLog*>(d + ((rt->stage_bytes + 255) / 256) * 256);
+    if (hipHostMalloc(&rt->hstage, rt->stage_bytes, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&rt->hlog), sizeof(agile_fault),
+                      hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&rt->upload_done, hipEventDisableTiming) != hipSuccess) {
+        agile_rt_destroy(rt);
+        return AGILE_ENOMEM;
+    }
+    if (launch_log_reset(rt->d_log, nullptr) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        agile_rt_destroy(rt);
+        return AGILE_EDEVICE;
+    }
+    *out = rt;
+    return AGILE_OK;
+}
+
+int agile_rt_destroy(agile_rt* rt) {
+    if (!rt) return AGILE_OK;
+    DeviceGuard dg(rt->device);
+    int rc = AGILE_OK;
+    if (hipDeviceSynchronize() != hipSuccess) rc = AGILE_EDEVICE;
+    if (rt->upload_done) (void)hipEventDestroy(rt->upload_done);
+    if (rt->hstage) (void)hipHostFree(rt->hstage);
+    if (rt->hlog) (void)hipHostFree(rt->hlog);
+    if (rt->dmem) (void)hipFree(rt->dmem);
+    delete rt;
+    return rc;
+}
+
+static int check_range(uint64_t base, uint64_t size, uint32_t kind) {
+    if (kind > AGILE_KIND_MMIO || size < 1 || size > U64MAX - base) return AGILE_EINVAL;
+    return AGILE_OK;
+}
+
+int agile_rt_insert(agile_rt* rt, uint64_t base, uint64_t size, uint32_t kind, int32_t* out_id) {
+    if (!rt) return AGILE_EINVAL;
+    int rc = check_range(base, size, kind);
+    if (rc != AGILE_OK) return rc;
+    if (rt->entries.size() >= rt->capacity || rt->next_id > MAX_ID) return AGILE_ENOSPC;
+    const uint64_t end = base + size;
+    auto& E = rt->entries;
+    auto it = std::upper_bound(E.begin(), E.end(), base,
+                               [](uint64_t v, const Entry& e) { return v < e.base; });
+    if (it != E.begin() && std::prev(it)->end > base) return AGILE_EOVERLAP;
+    if (it != E.end() && it->base < end) return AGILE_EOVERLAP;
+    const int32_t id = rt->next_id++;
+    E.insert(it, Entry{base, end, id, (uint8_t)kind});
+    rt->by_id[id] = base;
+    rt->dirty = true;
+    if (out_id) *out_id = id;
+    return AGILE_OK;
+}
+
+int agile_rt_insert_many(agile_rt* rt, const uint64_t* base, const uint64_t* size,
+                         const uint8_t* kind, uint32_t n, int32_t* out_ids) {
+    if (!rt) return AGILE_EINVAL;
+    if (n == 0) return AGILE_OK;
+    if (!base || !size || !kind) return AGILE_EINVAL;
+    for (uint32_t i = 0; i < n; ++i) {
+        int rc = check_range(base[i], size[i], kind[i]);
+        if (rc != AGILE_OK) return rc;
+    }
+    if ((uint64_t)rt->entries.size() + n > rt->capacity ||
+        (int64_t)rt->next_id + (int64_t)n - 1 > MAX_ID)
+        return AGILE_ENOSPC;
+    std::vector<Entry> add(n);
+    for (uint32_t i = 0; i < n; ++i)
+        add[i] = Entry{base[i], base[i] + size[i], rt->next_id + (int32_t)i, kind[i]};
+    std::vector<Entry> merged;
+    merged.reserve(rt->entries.size() + n);
+    std::vector<Entry> sorted_add = add;
+    std::sort(sorted_add.begin(), sorted_add.end(),
+              [](const Entry& a, const Entry& b) { return a.base < b.base; });
+    std::merge(rt->entries.begin(), rt->entries.end(), sorted_add.begin(), sorted_add.end(),
+               std::back_inserter(merged),
+               [](const Entry& a, const Entry& b) { return a.base < b.base; });
+    for (size_t i = 1; i < merged.size(); ++i)
+        if (merged[i - 1].end > merged[i].base) return AGILE_EOVERLAP;
+    rt->entries.swap(merged);
+    for (uint32_t i = 0; i < n; ++i) {
+        rt->by_id[add[i].id] = add[i].base;
+        if (out_ids) out_ids[i] = add[i].id;
+    }
+    rt->next_id += (int32_t)n;
+    rt->dirty = true;
+    return AGILE_OK;
+}
+
+int agile_rt_remove(agile_rt* rt, int32_t id) {
+    if (!rt) return AGILE_EINVAL;
+    auto f = rt->by_id.find(id);
+    if (f == rt->by_id.end()) return AGILE_ENOENT;
+    const uint64_t b = f->second;
+    auto& E = rt->entries;
+    auto it = std::lower_bound(E.begin(), E.end(), b,
+                               [](const Entry& e, uint64_t v) { return e.base < v; });
+    if (it == E.end() || it->base != b) return AGILE_ENOENT;
+    E.erase(it);
+    rt->by_id.erase(f);
+    rt->dirty = true;
+    return AGILE_OK;
+}
+
+int agile_rt_count(const agile_rt* rt, uint32_t* out_n) {
+    if (!rt || !out_n) return AGILE_EINVAL;
+    *out_n = (uint32_t)rt->entries.size();
+    return AGILE_OK;
+}
+
+int agile_rt_sync(agile_rt* rt, void* stream) {
+    if (!rt) return AGILE_EINVAL;
+    DeviceGuard dg(rt->device);
+    if (!dg.ok) return AGILE_EDEVICE;
+    return prepare(rt, static_cast<hipStream_t>(stream));
+}
+
+int agile_validate_ptrs(agile_rt* rt, const agile_ptr* d_q, uint64_t n, uint8_t* d_verdict,
+                        int32_t* d_owner, void* stream) {
+    if (!rt) return AGILE_EINVAL;
+    if (n == 0) return AGILE_OK;
+    if (!d_q || !d_verdict || !d_owner || ((uint64_t)d_q & 15)) return AGILE_EINVAL;
+    DeviceGuard dg(rt->device);
+    if (!dg.ok) return AGILE_EDEVICE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int rc = prepare(rt, s);
+    if (rc != AGILE_OK) return rc;
+    if (launch_validate(rt->tab, rt->info, rt->lds_budget, d_q, n, d_verdict, d_owner, s) !=
+        hipSuccess)
+        return AGILE_EDEVICE;
+    return AGILE_OK;
+}
+
+static bool policy_ok(int policy) {
+    return policy == AGILE_POLICY_SUPPRESS_LOG || policy == AGILE_POLICY_SUPPRESS_ONLY;
+}
+
+int agile_guarded_copy(agile_rt* rt, void* d_dst, const void* d_src, uint64_t nbytes, int policy,
+                       void* stream) {
+    if (!rt || !policy_ok(policy)) return AGILE_EINVAL;
+    DeviceGuard dg(rt->device);
+    if (!dg.ok) return AGILE_EDEVICE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int rc = prepare(rt, s);
+    if (rc != AGILE_OK) return rc;
+    const unsigned long long seq = rt->seq++;
+    if (launch_copy(true, rt->tab, rt->d_log, d_dst, d_src, nbytes, seq,
+                    policy == AGILE_POLICY_SUPPRESS_LOG, rt->info, s) != hipSuccess)
+        return AGILE_EDEVICE;
+    return AGILE_OK;
+}
+
+int agile_guarded_triad(agile_rt* rt, float* d_a, const float* d_b, const float* d_c, float s_,
+                        uint64_t n, int policy, void* stream) {
+    if (!rt || !policy_ok(policy)) return AGILE_EINVAL;
+    if ((((uint64_t)d_a | (uint64_t)d_b | (uint64_t)d_c) & 3) || n > (U64MAX >> 3))
+        return AGILE_EINVAL;
+    DeviceGuard dg(rt->device);
+    if (!dg.ok) return AGILE_EDEVICE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int rc = prepare(rt, s);
+    if (rc != AGILE_OK) return rc;
+    const unsigned long long seq = rt->seq++;
+    if (launch_triad(true, rt->tab, rt->d_log, d_a, d_b, d_c, s_, n, seq,
+                     policy == AGILE_POLICY_SUPPRESS_LOG, rt->info, s) != hipSuccess)
+        return AGILE_EDEVICE;
+    return AGILE_OK;
+}
+
+static int rows_args_ok(uint64_t row_bytes, uint64_t n, int dtype, const void* a, const void* b,
+                        uint32_t* w) {
+    if (dtype != AGILE_DTYPE_F32 && dtype != AGILE_DTYPE_F64) return AGILE_EINVAL;
+    *w = dtype == AGILE_DTYPE_F32 ? 4 : 8;
+    if (row_bytes == 0 || row_bytes % *w || row_bytes > (1ull << 40)) return AGILE_EINVAL;
+    const uint64_t D = row_bytes / *w;
+    if (n > 0 && D > ((1ull << 62) - 1) / n) return AGILE_EINVAL;
+    if ((((uint64_t)a | (uint64_t)b) & (*w - 1))) return AGILE_EINVAL;
+    return AGILE_OK;
+}
+
+int agile_guarded_gather(agile_rt* rt, void* d_out, const void* d_table, uint64_t row_bytes,
+                         const int64_t* d_idx, uint64_t n, int dtype, int policy, void* stream) {
+    if (!rt || !policy_ok(policy)) return AGILE_EINVAL;
+    uint32_t w;
+    int rc = rows_args_ok(row_bytes, n, dtype, d_out, d_table, &w);
+    if (rc != AGILE_OK) return rc;
+    if ((uint64_t)d_idx & 7) return AGILE_EINVAL;
+    DeviceGuard dg(rt->device);
+    if (!dg.ok) return AGILE_EDEVICE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = prepare(rt, s);
+    if (rc != AGILE_OK) return rc;
+    const unsigned long long seq = rt->seq++;
+    if (launch_gather(true, rt->tab, rt->d_log, d_out, d_table, row_bytes, d_idx, n, w, seq,
+                      policy == AGILE_POLICY_SUPPRESS_LOG, rt->info, s) != hipSuccess)
+        return AGILE_EDEVICE;
+    return AGILE_OK;
+}
+
+int agile_guarded_scatter(agile_rt* rt, void* d_dst, uint64_t row_bytes, const int64_t* d_idx,
+                          const void* d_src, uint64_t n, int dtype, int accumulate, int policy,
+                          void* stream) {
+    if (!rt || !policy_ok(policy) || (accumulate != 0 && accumulate != 1)) return AGILE_EINVAL;
+    uint32_t w;
+    int rc = rows_args_ok(row_bytes, n, dtype, d_dst, d_src, &w);
+    if (rc != AGILE_OK) return rc;
+    if ((uint64_t)d_idx & 7) return AGILE_EINVAL;
+    DeviceGuard dg(rt->device);
+    if (!dg.ok) return AGILE_EDEVICE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = prepare(rt, s);
+    if (rc != AGILE_OK) return rc;
+    const unsigned long long seq = rt->seq++;
+    if (launch_scatter(true, rt->tab, rt->d_log, d_dst, row_bytes, d_idx, d_src, n, w, accumulate,
+                       seq, policy == AGILE_POLICY_SUPPRESS_LOG, rt->info, s) != hipSuccess)
+        return AGILE_EDEVICE;
+    return AGILE_OK;
+}
+
+int agile_fault_log_read(agile_rt* rt, agile_fault* out, int clear, void* stream) {
+    if (!rt || !out) return AGILE_EINVAL;
+    DeviceGuard dg(rt->device);
+    if (!dg.ok) return AGILE_EDEVICE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (hipMemcpyAsync(rt->hlog, rt->d_log, sizeof(agile_fault), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return AGILE_EDEVICE;
+    *out = *rt->hlog;
+    if (clear && launch_log_reset(rt->d_log, s) != hipSuccess) return AGILE_EDEVICE;
+    return out->count ? AGILE_EFAULTED : AGILE_OK;
+}
+
+// ---- unguarded twins ------------------------------------------------------------------
+static DevInfo current_info() {
+    static thread_local int cached_dev = -1;
+    static thread_local DevInfo cached{};
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (dev != cached_dev) {
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, dev) == hipSuccess) {
+            cached.num_cu = p.multiProcessorCount;
+            cached.lds_per_block = p.sharedMemPerBlock;
+            cached.lds_per_cu = p.maxSharedMemoryPerMultiProcessor;
+            cached_dev = dev;
+        } else {
+            cached.num_cu = 1;
+        }
+    }
+    return cached;
+}
+
+int agile_unguarded_copy(void* d_dst, const void* d_src, uint64_t nbytes, void* stream) {
+    if (nbytes && (!d_dst || !d_src)) return AGILE_EINVAL;
+    return launch_copy(false, DevTable{}, nullptr, d_dst, d_src, nbytes, 0, 0, current_info(),
+                       static_cast<hipStream_t>(stream)) == hipSuccess
+               ? AGILE_OK
+               : AGILE_EDEVICE;
+}
+
+int agile_unguarded_triad(float* d_a, const float* d_b, const float* d_c, float s_, uint64_t n,
+                          void* stream) {
+    if (n && (!d_a || !d_b || !d_c)) return AGILE_EINVAL;
+    if (((uint64_t)d_a | (uint64_t)d_b | (uint64_t)d_c) & 3) return AGILE_EINVAL;
+    return launch_triad(false, DevTable{}, nullptr, d_a, d_b, d_c, s_, n, 0, 0, current_info(),
+                        static_cast<hipStream_t>(stream)) == hipSuccess
+               ? AGILE_OK
+               : AGILE_EDEVICE;
+}
+
+int agile_unguarded_gather(void* d_out, const void* d_table, uint64_t row_bytes,
+                           const int64_t* d_idx, uint64_t n, int dtype, void* stream) {
+    uint32_t w;
+    int rc = rows_args_ok(row_bytes, n, dtype, d_out, d_table, &w);
+    if (rc != AGILE_OK) return rc;
+    if (n && (!d_out || !d_table || !d_idx)) return AGILE_EINVAL;
+    return launch_gather(false, DevTable{}, nullptr, d_out, d_table, row_bytes, d_idx, n, w, 0, 0,
+                         current_info(), static_cast<hipStream_t>(stream)) == hipSuccess
+               ? AGILE_OK
+               : AGILE_EDEVICE;
+}
+
+int agile_unguarded_scatter(void* d_dst, uint64_t row_bytes, const int64_t* d_idx,
+                            const void* d_src, uint64_t n, int dtype, int accumulate,
+                            void* stream) {
+    uint32_t w;
+    if (accumulate != 0 && accumulate != 1) return AGILE_EINVAL;
+    int rc = rows_args_ok(row_bytes, n, dtype, d_dst, d_src, &w);
+    if (rc != AGILE_OK) return rc;
+    if (n && (!d_dst || !d_src || !d_idx)) return AGILE_EINVAL;
+    return launch_scatter(false, DevTable{}, nullptr, d_dst, row_bytes, d_idx, d_src, n, w,
+                          accumulate, 0, 0, current_info(),
+                          static_cast<hipStream_t>(stream)) == hipSuccess
+               ? AGILE_OK
+               : AGILE_EDEVICE;
+}
+
+}  // extern "C"

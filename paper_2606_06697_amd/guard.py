@@ -1,0 +1,261 @@
+"""Python binding of libagile_guard.so (argument marshalling only).
+
+Every function here has the name of the C entry point it forwards to (see
+``include/agile_guard.h``); pointers may be given as torch tensors (their ``data_ptr()``) or
+as raw integer addresses, streams as ``torch.cuda.Stream``, raw handles or ``None`` (the
+current torch stream). Nothing is computed in Python: all guard work runs in the library's
+HIP kernels, and if the library is missing every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libagile_guard.so")
+
+AGILE_OK, AGILE_EINVAL, AGILE_ENOMEM, AGILE_EOVERLAP = 0, -1, -2, -3
+AGILE_ENOENT, AGILE_ENOSPC, AGILE_EDEVICE, AGILE_EFAULTED = -4, -5, -6, -7
+KIND_USER, KIND_PROTECTED, KIND_MMIO = 0, 1, 2
+ALLOW, V_PROTECTED, V_STRADDLE, V_UNMAPPED, V_CROSS_ALLOC = 0, 1, 2, 3, 4
+POLICY_SUPPRESS_LOG, POLICY_SUPPRESS_ONLY = 0, 1
+OP_COPY, OP_TRIAD, OP_GATHER, OP_SCATTER, OP_SCATTER_ADD = 1, 2, 3, 4, 5
+DTYPE_F32, DTYPE_F64 = 0, 1
+NO_SEQ = (1 << 64) - 1
+
+
+class AgileError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} ({code})")
+
+
+class agile_fault(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_uint64), ("first_seq", ctypes.c_uint64),
+                ("first_elem", ctypes.c_uint64), ("first_addr", ctypes.c_uint64),
+                ("first_width", ctypes.c_uint32), ("first_op", ctypes.c_uint32),
+                ("first_operand", ctypes.c_uint32), ("first_verdict", ctypes.c_uint32),
+                ("first_owner", ctypes.c_int32), ("reserved", ctypes.c_uint32)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return d
+
+
+_u64, _u32, _i32, _int, _vp = (ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_int,
+                               ctypes.c_void_p)
+_SIGS = {
+    "agile_strerror": (ctypes.c_char_p, [_int]),
+    "agile_rt_create": (_int, [ctypes.POINTER(_vp), _u32, _int]),
+    "agile_rt_destroy": (_int, [_vp]),
+    "agile_rt_insert": (_int, [_vp, _u64, _u64, _u32, ctypes.POINTER(_i32)]),
+    "agile_rt_insert_many": (_int, [_vp, _vp, _vp, _vp, _u32, _vp]),
+    "agile_rt_remove": (_int, [_vp, _i32]),
+    "agile_rt_count": (_int, [_vp, ctypes.POINTER(_u32)]),
+    "agile_rt_sync": (_int, [_vp, _vp]),
+    "agile_validate_ptrs": (_int, [_vp, _vp, _u64, _vp, _vp, _vp]),
+    "agile_guarded_copy": (_int, [_vp, _vp, _vp, _u64, _int, _vp]),
+    "agile_guarded_triad": (_int, [_vp, _vp, _vp, _vp, ctypes.c_float, _u64, _int, _vp]),
+    "agile_guarded_gather": (_int, [_vp, _vp, _vp, _u64, _vp, _u64, _int, _int, _vp]),
+    "agile_guarded_scatter": (_int, [_vp, _vp, _u64, _vp, _vp, _u64, _int, _int, _int, _vp]),
+    "agile_fault_log_read": (_int, [_vp, ctypes.POINTER(agile_fault), _int, _vp]),
+    "agile_unguarded_copy": (_int, [_vp, _vp, _u64, _vp]),
+    "agile_unguarded_triad": (_int, [_vp, _vp, _vp, ctypes.c_float, _u64, _vp]),
+    "agile_unguarded_gather": (_int, [_vp, _vp, _u64, _vp, _u64, _int, _vp]),
+    "agile_unguarded_scatter": (_int, [_vp, _u64, _vp, _vp, _u64, _int, _int, _vp]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(there is no fallback path)")
+        L = ctypes.CDLL(LIB_PATH, mode=ctypes.RTLD_GLOBAL)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def agile_strerror(code: int) -> str:
+    return lib().agile_strerror(int(code)).decode()
+
+
+strerror = agile_strerror
+
+
+def _ptr(x) -> int:
+    if x is None:
+        return 0
+    if isinstance(x, torch.Tensor):
+        return x.data_ptr()
+    return int(x) & ((1 << 64) - 1)
+
+
+def _stream(s):
+    if s is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(s, torch.cuda.Stream):
+        return s.cuda_stream
+    return int(s)
+
+
+def _check(rc: int, where: str, ok=(AGILE_OK,)):
+    if rc not in ok:
+        raise AgileError(rc, where)
+    return rc
+
+
+# ---- C entry points ----------------------------------------------------------------------
+def agile_rt_create(capacity: int, device: int = 0) -> int:
+    h = _vp()
+    _check(lib().agile_rt_create(ctypes.byref(h), capacity, device), "agile_rt_create")
+    return h.value
+
+
+def agile_rt_destroy(rt: int) -> None:
+    _check(lib().agile_rt_destroy(rt), "agile_rt_destroy")
+
+
+def agile_rt_insert(rt: int, base: int, size: int, kind: int) -> int:
+    out = _i32()
+    _check(lib().agile_rt_insert(rt, base & ((1 << 64) - 1), size, kind, ctypes.byref(out)),
+           "agile_rt_insert")
+    return out.value
+
+
+def agile_rt_insert_many(rt: int, base, size, kind) -> "torch.Tensor":
+    """base/size: int64 or uint64 CPU tensors (bit patterns), kind: uint8; returns int32 ids."""
+    base = torch.as_tensor(base).contiguous().cpu()
+    size = torch.as_tensor(size).contiguous().cpu()
+    kind = torch.as_tensor(kind).to(torch.uint8).contiguous().cpu()
+    n = base.numel()
+    ids = torch.empty(n, dtype=torch.int32)
+    _check(lib().agile_rt_insert_many(rt, base.data_ptr(), size.data_ptr(), kind.data_ptr(), n,
+                                      ids.data_ptr()), "agile_rt_insert_many")
+    return ids
+
+
+def agile_rt_remove(rt: int, rid: int) -> None:
+    _check(lib().agile_rt_remove(rt, rid), "agile_rt_remove")
+
+
+def agile_rt_count(rt: int) -> int:
+    out = _u32()
+    _check(lib().agile_rt_count(rt, ctypes.byref(out)), "agile_rt_count")
+    return out.value
+
+
+def agile_rt_sync(rt: int, stream=None) -> None:
+    _check(lib().agile_rt_sync(rt, _stream(stream)), "agile_rt_sync")
+
+
+def agile_validate_ptrs(rt: int, q, n: int, verdict, owner, stream=None) -> None:
+    _check(lib().agile_validate_ptrs(rt, _ptr(q), n, _ptr(verdict), _ptr(owner), _stream(stream)),
+           "agile_validate_ptrs")
+
+
+def agile_guarded_copy(rt: int, dst, src, nbytes: int, policy: int = 0, stream=None) -> None:
+    _check(lib().agile_guarded_copy(rt, _ptr(dst), _ptr(src), nbytes, policy, _stream(stream)),
+           "agile_guarded_copy")
+
+
+def agile_guarded_triad(rt: int, a, b, c, s: float, n: int, policy: int = 0, stream=None) -> None:
+    _check(lib().agile_guarded_triad(rt, _ptr(a), _ptr(b), _ptr(c), s, n, policy,
+                                     _stream(stream)), "agile_guarded_triad")
+
+
+def agile_guarded_gather(rt: int, out, table, row_bytes: int, idx, n: int, dtype: int = 0,
+                         policy: int = 0, stream=None) -> None:
+    _check(lib().agile_guarded_gather(rt, _ptr(out), _ptr(table), row_bytes, _ptr(idx), n, dtype,
+                                      policy, _stream(stream)), "agile_guarded_gather")
+
+
+def agile_guarded_scatter(rt: int, dst, row_bytes: int, idx, src, n: int, dtype: int = 0,
+                          accumulate: int = 0, policy: int = 0, stream=None) -> None:
+    _check(lib().agile_guarded_scatter(rt, _ptr(dst), row_bytes, _ptr(idx), _ptr(src), n, dtype,
+                                       accumulate, policy, _stream(stream)),
+           "agile_guarded_scatter")
+
+
+def agile_fault_log_read(rt: int, clear: bool = False, stream=None):
+    """Returns (status, record dict); status is AGILE_OK or AGILE_EFAULTED."""
+    f = agile_fault()
+    rc = _check(lib().agile_fault_log_read(rt, ctypes.byref(f), int(bool(clear)),
+                                           _stream(stream)), "agile_fault_log_read",
+                ok=(AGILE_OK, AGILE_EFAULTED))
+    return rc, f.as_dict()
+
+
+def agile_unguarded_copy(dst, src, nbytes: int, stream=None) -> None:
+    _check(lib().agile_unguarded_copy(_ptr(dst), _ptr(src), nbytes, _stream(stream)),
+           "agile_unguarded_copy")
+
+
+def agile_unguarded_triad(a, b, c, s: float, n: int, stream=None) -> None:
+    _check(lib().agile_unguarded_triad(_ptr(a), _ptr(b), _ptr(c), s, n, _stream(stream)),
+           "agile_unguarded_triad")
+
+
+def agile_unguarded_gather(out, table, row_bytes: int, idx, n: int, dtype: int = 0,
+                           stream=None) -> None:
+    _check(lib().agile_unguarded_gather(_ptr(out), _ptr(table), row_bytes, _ptr(idx), n, dtype,
+                                        _stream(stream)), "agile_unguarded_gather")
+
+
+def agile_unguarded_scatter(dst, row_bytes: int, idx, src, n: int, dtype: int = 0,
+                            accumulate: int = 0, stream=None) -> None:
+    _check(lib().agile_unguarded_scatter(_ptr(dst), row_bytes, _ptr(idx), _ptr(src), n, dtype,
+                                         accumulate, _stream(stream)), "agile_unguarded_scatter")
+
+
+class RangeTable:
+    """Owning wrapper of one table handle (destroyed on close or garbage collection)."""
+
+    def __init__(self, capacity: int, device: int = 0):
+        self.handle = agile_rt_create(capacity, device)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            agile_rt_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def insert(self, base: int, size: int, kind: int = KIND_USER) -> int:
+        return agile_rt_insert(self.handle, base, size, kind)
+
+    def insert_tensor(self, t: torch.Tensor, kind: int = KIND_USER) -> int:
+        """Register a tensor's bytes as one range."""
+        return self.insert(t.data_ptr(), t.numel() * t.element_size(), kind)
+
+    def insert_many(self, base, size, kind):
+        return agile_rt_insert_many(self.handle, base, size, kind)
+
+    def remove(self, rid: int) -> None:
+        agile_rt_remove(self.handle, rid)
+
+    def __len__(self):
+        return agile_rt_count(self.handle)
+
+    def fault_log(self, clear: bool = False, stream=None):
+        return agile_fault_log_read(self.handle, clear, stream)
