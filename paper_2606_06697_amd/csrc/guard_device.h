@@ -1,6 +1,8 @@
 // Device-side data layout and helpers shared by the guard kernels (gfx950, wave64).
 //
 // Table image (built on the host from the sorted range list, uploaded in stream order):
+//   radix[r]    u32  search index over the LDS-resident splitters (see DevTable)
+//   nrec[b]     16 B the bucket's record with bit-packed offsets (see DevTable), when they fit
 //   split64[b]  u64  base of the first range of bucket b (buckets hold 2 consecutive
 //                    ranges in address order), nb = ceil(n/2) entries
 //   split32[b]  u32  (split64[b] - gmin) >> shift, present when every bucket base is a
@@ -36,11 +38,34 @@ struct DevTable {
     const uint64_t* split64;
     const uint32_t* split32;
     const PairRec* rec;
+    const uint32_t* radix;  // validation search index, see below
     uint64_t gmin;
     uint32_t nb;          // number of buckets (0 for an empty table)
     uint32_t shift;
     uint32_t compressed;  // split32 valid
+    // Validation search geometry. The LDS holds top[k] = splitter(k << rlog2), k < ntop, then
+    // `pad` sentinels of the largest key value, then radix[r] = number of top entries below
+    // gmin + (r << rsh), r <= nr (radix[nr] = ntop): an address with offset d = addr - gmin
+    // has its answer among top[radix[r] ..], r = min(d >> rsh, nr - 1), at most 2^rlevels - 1
+    // entries on. With compressed keys, r = min(key >> xs, nr - 1) (xs = rsh - shift, capped at
+    // 31; nr == 1 whenever it would exceed 31). pad = 2^lift, lift >= rlevels.
+    uint32_t ntop;
+    uint32_t rlog2;
+    uint32_t nr;
+    uint32_t rsh;
+    uint32_t xs;
+    uint32_t rlevels;
+    uint32_t lift;
     uint32_t pad;
+    uint32_t lds_bytes;   // LDS one validation workgroup needs (top + sentinels + radix)
+    // Packed records (validation only, present when narrow != 0; then rlog2 == 0): per bucket
+    // 16 bytes {u32 lo, u32 hi, u32 meta0, u32 meta1} with offsets relative to the bucket base:
+    // lo = (second range's base >> sb) | (first range's end << w1), hi = second range's end.
+    const uint4* nrec;
+    uint32_t narrow;
+    uint32_t sb;
+    uint32_t w1;
+    uint32_t pad2;
 };
 
 // Device copy of the public fault log (same field order as agile_fault) + per-launch scratch.

@@ -13,17 +13,11 @@ struct DevInfo {
     size_t lds_per_cu;
 };
 
-// Search geometry for validation: the LDS holds `ntop` splitters, every (1 << rlog2)-th one.
-struct SearchGeom {
-    uint32_t ntop;
-    uint32_t rlog2;
-    size_t lds_bytes;
-};
-SearchGeom validate_geometry(const DevTable& t, const DevInfo& d, size_t lds_budget);
+// Maximum number of radix entries (plus one) the validation index may use.
+constexpr uint32_t MAX_RADIX = (1u << 14) + 1;
 
-hipError_t launch_validate(const DevTable& t, const DevInfo& d, size_t lds_budget,
-                           const void* q, uint64_t n, uint8_t* verdict, int32_t* owner,
-                           hipStream_t s);
+hipError_t launch_validate(const DevTable& t, const DevInfo& d, const void* q, uint64_t n,
+                           uint8_t* verdict, int32_t* owner, hipStream_t s);
 
 hipError_t launch_copy(bool guard, const DevTable& t, DevLog* log, void* dst, const void* src,
                        uint64_t n, unsigned long long seq, int logon, const DevInfo& d,

@@ -13,7 +13,7 @@
 #include <unordered_map>
 #include <vector>
 
-#include "../../include/agile_guard.h"
+#include "agile_guard.h"
 #include "launch.h"
 
 using namespace agile;
@@ -54,11 +54,14 @@ struct agile_rt {
     unsigned long long seq = 0;
     DevInfo info{};
     size_t lds_budget = 0;
+    bool wide_only = false;  // never build narrow records (AGILE_WIDE_RECORDS=1)
     // device image
     void* dmem = nullptr;
     uint64_t* d_split64 = nullptr;
     uint32_t* d_split32 = nullptr;
     PairRec* d_rec = nullptr;
+    uint32_t* d_radix = nullptr;
+    uint4* d_nrec = nullptr;
     DevLog* d_log = nullptr;
     DevTable tab{};
     // pinned staging
@@ -70,8 +73,134 @@ struct agile_rt {
     std::vector<hipStream_t> streams_used;
 };
 
+// Image layout: split64 | split32 | (64-byte aligned) rec | radix
+static size_t rec_offset(uint32_t cap_nb) {
+    return (((size_t)cap_nb * 12 + 63) / 64) * 64;
+}
+static size_t radix_offset(uint32_t cap_nb) {
+    return rec_offset(cap_nb) + (size_t)cap_nb * sizeof(PairRec);
+}
+static size_t nrec_offset(uint32_t cap_nb) {
+    return radix_offset(cap_nb) + (((size_t)MAX_RADIX * 4 + 63) / 64) * 64;
+}
 static size_t image_bytes(uint32_t cap_nb) {
-    return (size_t)cap_nb * 8 + (size_t)cap_nb * 4 + 64 + (size_t)cap_nb * sizeof(PairRec);
+    return nrec_offset(cap_nb) + (size_t)cap_nb * 16;
+}
+
+static uint32_t bitlen(uint64_t x) {
+    uint32_t b = 0;
+    while (x) {
+        ++b;
+        x >>= 1;
+    }
+    return b;
+}
+
+static uint32_t ctz64(uint64_t x) {
+    uint32_t c = 0;
+    while (c < 64 && !((x >> c) & 1)) ++c;
+    return c;
+}
+
+// Packed 16-byte records: relative to the bucket base, the second range's base in units of 2^sb
+// and the first range's end share one 32-bit word, the second range's end takes another.
+static void build_narrow(DevTable& t, const uint64_t* s64, const PairRec* rec, uint32_t* nrec) {
+    t.narrow = 0;
+    const uint32_t nb = t.nb;
+    if (nb == 0 || t.rlog2 != 0 || t.rlevels > 8) return;
+    uint32_t sb = 32;
+    uint64_t me0 = 0, me1 = 0;
+    for (uint32_t b = 0; b < nb; ++b) {
+        me0 = std::max(me0, rec[b].end0 - s64[b]);
+        if (rec[b].base1 != U64MAX) {
+            sb = std::min(sb, ctz64(rec[b].base1 - s64[b]));
+            me1 = std::max(me1, rec[b].end1 - s64[b]);
+        }
+    }
+    // a missing second range gets a base at or past the first end and an end of 0, so an
+    // address past the first range classifies as unmapped either way
+    auto ob1 = [&](uint32_t b) -> uint64_t {
+        return rec[b].base1 != U64MAX ? (rec[b].base1 - s64[b]) >> sb
+                                      : ((rec[b].end0 - s64[b]) + (1ull << sb) - 1) >> sb;
+    };
+    uint64_t mb1 = 0;
+    for (uint32_t b = 0; b < nb; ++b) mb1 = std::max(mb1, ob1(b));
+    const uint32_t w1 = bitlen(mb1), w2 = bitlen(me0), w3 = bitlen(me1);
+    if (w1 + w2 > 32 || w3 > 32) return;
+    for (uint32_t b = 0; b < nb; ++b) {
+        const bool two = rec[b].base1 != U64MAX;
+        nrec[4 * b + 0] = (uint32_t)(ob1(b) | ((rec[b].end0 - s64[b]) << w1));
+        nrec[4 * b + 1] = two ? (uint32_t)(rec[b].end1 - s64[b]) : 0u;
+        nrec[4 * b + 2] = rec[b].meta0;
+        nrec[4 * b + 3] = two ? rec[b].meta1 : 0u;
+    }
+    t.narrow = 1;
+    t.sb = sb;
+    t.w1 = w1;
+}
+
+
+// Validation search geometry for nb buckets with first bases s64[]: how many splitters the LDS
+// holds (every 2^rlog2-th) and a radix index over them that bounds each lookup to a run of at
+// most 2^rlevels - 1 splitters; the LDS array carries 2^rlevels sentinels after the splitters.
+static uint32_t lift_levels(uint32_t rlevels) {
+    // the unrolled lifting exists for 2, 4, 6 and 8 levels; reading more levels than needed
+    // stays correct (the predicate is monotone over the sentinel padding)
+    if (rlevels <= 8) return rlevels <= 2 ? 2 : (rlevels + 1) & ~1u;
+    return rlevels;
+}
+
+static void search_geometry(DevTable& t, const uint64_t* s64, uint32_t* radix, size_t budget) {
+    const uint32_t nb = t.nb;
+    const size_t ks = t.compressed ? 4 : 8;
+    t.rlog2 = 0;
+    if (nb == 0) {
+        t.ntop = 0;
+        t.nr = 1;
+        t.rsh = t.shift;
+        t.xs = 0;
+        t.rlevels = 0;
+        t.lift = 0;
+        t.pad = 1;
+        radix[0] = radix[1] = 0;
+        t.lds_bytes = 16 + 8;
+        return;
+    }
+    const uint64_t gmin = s64[0];
+    for (uint32_t rlog2 = 0; rlog2 < 32; ++rlog2) {
+        const uint32_t ntop = (uint32_t)(((uint64_t)nb + (1ull << rlog2) - 1) >> rlog2);
+        const uint64_t span = s64[(uint64_t)(ntop - 1) << rlog2] - gmin;
+        const uint32_t bits = bitlen(span);
+        for (int R = 14; R >= 0; --R) {
+            if (R > 0 && (1ull << (R - 1)) >= ntop) continue;  // no more radix bins than splitters
+            const uint32_t rsh = std::max<uint32_t>(bits > (uint32_t)R ? bits - R : 0, t.shift);
+            const uint32_t nr = (uint32_t)(span >> rsh) + 1;
+            if ((size_t)(nr + 1) * 4 + (size_t)ntop * ks > budget) continue;
+            uint32_t k = 0, maxm = 0;
+            for (uint32_t r = 0; r < nr; ++r) {
+                const uint64_t bound = gmin + ((uint64_t)r << rsh);
+                while (k < ntop && s64[(uint64_t)k << rlog2] < bound) ++k;
+                radix[r] = k;
+            }
+            radix[nr] = ntop;
+            for (uint32_t r = 0; r < nr; ++r) maxm = std::max(maxm, radix[r + 1] - radix[r]);
+            const uint32_t rlevels = bitlen(maxm);
+            const uint32_t lift = lift_levels(rlevels);
+            const size_t top_bytes = ((((size_t)ntop + (1ull << lift)) * ks + 15) / 16) * 16;
+            const size_t need = top_bytes + (size_t)(nr + 1) * 4;
+            if (need > budget) continue;
+            t.rlog2 = rlog2;
+            t.ntop = ntop;
+            t.nr = nr;
+            t.rsh = rsh;
+            t.xs = std::min<uint32_t>(rsh - t.shift, 31);
+            t.rlevels = rlevels;
+            t.lift = lift;
+            t.pad = 1u << lift;
+            t.lds_bytes = (uint32_t)need;
+            return;
+        }
+    }
 }
 
 static void note_stream(agile_rt* rt, hipStream_t s) {
@@ -92,8 +221,9 @@ static int upload(agile_rt* rt, hipStream_t s) {
     uint8_t* h = static_cast<uint8_t*>(rt->hstage);
     uint64_t* s64 = reinterpret_cast<uint64_t*>(h);
     uint32_t* s32 = reinterpret_cast<uint32_t*>(h + (size_t)rt->cap_nb * 8);
-    PairRec* rec = reinterpret_cast<PairRec*>(h + (size_t)rt->cap_nb * 12 + 64 -
-                                              (((size_t)rt->cap_nb * 12) % 64));
+    PairRec* rec = reinterpret_cast<PairRec*>(h + rec_offset(rt->cap_nb));
+    uint32_t* radix = reinterpret_cast<uint32_t*>(h + radix_offset(rt->cap_nb));
+    uint32_t* nrec = reinterpret_cast<uint32_t*>(h + nrec_offset(rt->cap_nb));
     const auto& E = rt->entries;
     for (uint32_t b = 0; b < nb; ++b) {
         const Entry& e0 = E[2 * b];
@@ -117,10 +247,12 @@ static int upload(agile_rt* rt, hipStream_t s) {
     t.split64 = rt->d_split64;
     t.split32 = rt->d_split32;
     t.rec = rt->d_rec;
+    t.radix = rt->d_radix;
     t.nb = nb;
     t.compressed = 0;
     if (nb > 0) {
         const uint64_t gmin = s64[0];
+        t.gmin = gmin;
         const uint64_t span = s64[nb - 1] - gmin;
         uint32_t sh = 0;
         while (sh < 63 && (span >> sh) > 0xFFFFFFFEull) ++sh;
@@ -130,10 +262,12 @@ static int upload(agile_rt* rt, hipStream_t s) {
         if (ok) {
             for (uint32_t b = 0; b < nb; ++b) s32[b] = (uint32_t)((s64[b] - gmin) >> sh);
             t.compressed = 1;
-            t.gmin = gmin;
             t.shift = sh;
         }
     }
+    search_geometry(t, s64, radix, std::min(rt->lds_budget, rt->info.lds_per_block));
+    t.nrec = rt->d_nrec;
+    if (!rt->wide_only) build_narrow(t, s64, rec, nrec);
     // make every other stream that used the handle finish with the old image first
     for (hipStream_t o : rt->streams_used) {
         if (o == s) continue;
@@ -155,9 +289,15 @@ static int upload(agile_rt* rt, hipStream_t s) {
         if (hipMemcpyAsync(rt->d_rec, rec, (size_t)nb * sizeof(PairRec), hipMemcpyHostToDevice, s) !=
             hipSuccess)
             return AGILE_EDEVICE;
-        if (hipEventRecord(rt->upload_done, s) != hipSuccess) return AGILE_EDEVICE;
-        rt->upload_pending = true;
     }
+    if (t.narrow &&
+        hipMemcpyAsync(rt->d_nrec, nrec, (size_t)nb * 16, hipMemcpyHostToDevice, s) != hipSuccess)
+        return AGILE_EDEVICE;
+    if (hipMemcpyAsync(rt->d_radix, radix, (size_t)(t.nr + 1) * 4, hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipEventRecord(rt->upload_done, s) != hipSuccess)
+        return AGILE_EDEVICE;
+    rt->upload_pending = true;
     rt->tab = t;
     rt->dirty = false;
     return AGILE_OK;
@@ -206,11 +346,12 @@ int agile_rt_create(agile_rt** out, uint32_t capacity, int device) {
     rt->info.num_cu = p.multiProcessorCount;
     rt->info.lds_per_block = p.sharedMemPerBlock;
     rt->info.lds_per_cu = p.maxSharedMemoryPerMultiProcessor;
-    rt->lds_budget = 128 * 1024;
+    rt->lds_budget = 160 * 1024;
     if (const char* e = std::getenv("AGILE_LDS_BUDGET")) {
         long v = std::strtol(e, nullptr, 10);
         if (v >= 1024) rt->lds_budget = (size_t)v;
     }
+    if (const char* e = std::getenv("AGILE_WIDE_RECORDS")) rt->wide_only = std::atoi(e) != 0;
     rt->stage_bytes = image_bytes(rt->cap_nb);
     const size_t dev_bytes = rt->stage_bytes + 256 + sizeof(DevLog);
     if (hipMalloc(&rt->dmem, dev_bytes) != hipSuccess) {
@@ -220,8 +361,9 @@ int agile_rt_create(agile_rt** out, uint32_t capacity, int device) {
     uint8_t* d = static_cast<uint8_t*>(rt->dmem);
     rt->d_split64 = reinterpret_cast<uint64_t*>(d);
     rt->d_split32 = reinterpret_cast<uint32_t*>(d + (size_t)rt->cap_nb * 8);
-    rt->d_rec = reinterpret_cast<PairRec*>(d + (size_t)rt->cap_nb * 12 + 64 -
-                                           (((size_t)rt->cap_nb * 12) % 64));
+    rt->d_rec = reinterpret_cast<PairRec*>(d + rec_offset(rt->cap_nb));
+    rt->d_radix = reinterpret_cast<uint32_t*>(d + radix_offset(rt->cap_nb));
+    rt->d_nrec = reinterpret_cast<uint4*>(d + nrec_offset(rt->cap_nb));
     rt->d_log = reinterpret_cast<DevLog*>(d + ((rt->stage_bytes + 255) / 256) * 256);
     if (hipHostMalloc(&rt->hstage, rt->stage_bytes, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&rt->hlog), sizeof(agile_fault),
@@ -349,8 +491,7 @@ int agile_validate_ptrs(agile_rt* rt, const agile_ptr* d_q, uint64_t n, uint8_t*
     hipStream_t s = static_cast<hipStream_t>(stream);
     int rc = prepare(rt, s);
     if (rc != AGILE_OK) return rc;
-    if (launch_validate(rt->tab, rt->info, rt->lds_budget, d_q, n, d_verdict, d_owner, s) !=
-        hipSuccess)
+    if (launch_validate(rt->tab, rt->info, d_q, n, d_verdict, d_owner, s) != hipSuccess)
         return AGILE_EDEVICE;
     return AGILE_OK;
 }

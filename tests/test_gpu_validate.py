@@ -87,9 +87,10 @@ def _boundary_queries(ot, rng):
 
 
 @pytest.mark.parametrize("seed", range(8))
-def test_exhaustive_boundaries_random_tables(seed):
+def test_exhaustive_boundaries_random_tables(seed, monkeypatch):
     """Byte-granular bases (uncompressed splitters), adjacency, kinds, top of address space."""
     need_gpu()
+    monkeypatch.setenv("AGILE_WIDE_RECORDS", "1" if seed % 2 else "0")
     rng = random.Random(seed)
     tw = Twin(512)
     pos = rng.choice([0, 1 << 40, U64_MAX - (1 << 20)])
@@ -134,9 +135,12 @@ def test_two_level_search_small_lds_budget(budget, monkeypatch):
     tw.close()
 
 
-def test_large_table_ragged_queries():
-    """65,536 ranges (8,192 protected) and a query count that is not a multiple of any tile."""
+@pytest.mark.parametrize("wide", ["0", "1"])
+def test_large_table_ragged_queries(wide, monkeypatch):
+    """65,536 ranges (8,192 protected) and a query count that is not a multiple of any tile,
+    with the packed 16-byte bucket records and with the general 32-byte ones."""
     need_gpu()
+    monkeypatch.setenv("AGILE_WIDE_RECORDS", wide)
     tb = make_table(65536, 8192, 1)
     tw = Twin(65536)
     tw.insert_table(tb)
