@@ -8,3 +8,4 @@ request loop.
 """
 from . import guard  # noqa: F401
 from .guard import *  # noqa: F401,F403
+from . import embedding  # noqa: F401

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB_NAME = "libagile_guard.so"
 LIB_PATH = os.path.join(HERE, LIB_NAME)
-SOURCES = ["runtime.hip", "k_validate.hip", "k_stream.hip", "k_gather.hip"]
+SOURCES = ["runtime.hip", "k_validate.hip", "k_stream.hip", "k_gather.hip", "k_scatter_add.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -61,7 +61,7 @@ def build(verbose: bool = False) -> str:
             print(r.stderr, file=sys.stderr)
         return obj
 
-    with cf.ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     tlib = torch_lib_dir()
     tmp = LIB_PATH + ".tmp"

@@ -228,4 +228,56 @@ __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long x)
     return x;
 }
 
+// ---- denial accounting shared by the data-dependent guarded kernels ----
+struct FaultAcc {
+    unsigned long long cnt = 0;
+    unsigned long long mk = ~0ull;
+    __device__ __forceinline__ void note(unsigned long long key) {
+        ++cnt;
+        mk = key < mk ? key : mk;
+    }
+};
+
+// Fold per-lane denials into the log; the last workgroup writes the smallest key's record.
+template <typename Payload>
+__device__ inline void fold_faults(FaultAcc acc, DevLog* log, const Payload& payload) {
+    __shared__ unsigned int s_last;
+    const unsigned long long c = wave_sum_u64(acc.cnt);
+    const unsigned long long m = wave_min_u64(acc.mk);
+    if ((threadIdx.x & 63u) == 0 && c) {
+        atomicAdd(&log->s_count, c);
+        atomicMin(&log->s_minkey, m);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned int ticket = atomicAdd(&log->s_done, 1u);
+        s_last = ticket == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (s_last && threadIdx.x == 0) {
+        __threadfence();
+        const unsigned long long total = atomicAdd(&log->s_count, 0ull);
+        const unsigned long long key = atomicMin(&log->s_minkey, ~0ull);
+        if (total) {
+            atomicAdd(&log->count, total);
+            payload(key);
+        }
+        log->s_count = 0;
+        log->s_minkey = ~0ull;
+        log->s_done = 0;
+        __threadfence();
+    }
+}
+
+__device__ inline void record_at(const DevTable& t, DevLog* log, unsigned long long seq,
+                                 unsigned long long elem, uint32_t operand, __int128 A, uint32_t w,
+                                 uint32_t op) {
+    uint32_t v = V_UNMAPPED;
+    int32_t o = -1;
+    const bool in_space = A >= 0 && A <= (__int128)U64MAX;
+    if (in_space) reason_lane(t, (uint64_t)A, w, v, o);
+    log_record(log, seq, elem, operand, (uint64_t)A, w, op, v, o);
+}
+
 }  // namespace agile

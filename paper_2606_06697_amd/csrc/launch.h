@@ -36,6 +36,10 @@ hipError_t launch_scatter(bool guard, const DevTable& t, DevLog* log, void* dst,
                           uint32_t w, int accumulate, unsigned long long seq, int logon,
                           const DevInfo& d, hipStream_t s);
 
+hipError_t launch_scatter_add(bool guard, const DevTable& t, DevLog* log, void* dst, uint64_t rb,
+                              const int64_t* idx, const void* src, uint64_t n, uint32_t w,
+                              unsigned long long seq, int logon, const DevInfo& d, hipStream_t s);
+
 hipError_t launch_log_reset(DevLog* log, hipStream_t s);
 
 }  // namespace agile
