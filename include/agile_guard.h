@@ -203,6 +203,65 @@ int agile_unguarded_scatter(void* d_dst, uint64_t row_bytes, const int64_t* d_id
                             const void* d_src, uint64_t n, int dtype, int accumulate,
                             void* stream);
 
+/* ---- batched multi-client requests (Section IV-B: a scheduler assigns each client to a worker;
+ * Section IV-C/IV-F: every pointer argument of a mediated request is checked against the
+ * calling client's own allocations before the real call). Many requests of many clients run in
+ * one persistent launch; each request is judged only against its own client's table. -------- */
+
+typedef struct agile_clients agile_clients; /* opaque: a fixed set of client tables */
+
+/* One request (host memory, 96 bytes). Every part is optional (a zero count skips it):
+ *  - validate: nptr pointer arguments at d_ptrs[ptr_off .. ptr_off + nptr) of the launch;
+ *  - copy:     guarded copy of copy_bytes bytes from copy_src to copy_dst;
+ *  - gather:   guarded gather of gather_n rows of gather_row_bytes bytes (fp32 elements) from
+ *              gather_table by the int64 indices at gather_idx into gather_out.
+ * All addresses are device addresses judged against client `client`'s table. */
+typedef struct {
+    uint32_t client;
+    uint32_t reserved0;
+    uint64_t ptr_off;
+    uint64_t nptr;
+    uint64_t copy_dst;
+    uint64_t copy_src;
+    uint64_t copy_bytes;
+    uint64_t gather_out;
+    uint64_t gather_table;
+    uint64_t gather_idx;
+    uint64_t gather_n;
+    uint32_t gather_row_bytes;
+    uint32_t reserved1;
+    uint64_t reserved2;
+} agile_request;
+
+/* Per-request result (device memory, 72 bytes), written when the request completes:
+ * verdict/arg/owner: the verdict of the lowest-index pointer argument that is not ALLOW, its
+ * index within the request and its owner (ALLOW, -1, -1 if all pass). fault: the denials of
+ * the request's copy and gather (count, and the smallest key; first_seq = the request's index
+ * in the launch; a copy's denials precede its gather's). done is set to 1 last. */
+typedef struct {
+    uint32_t verdict;
+    int32_t arg;
+    int32_t owner;
+    uint32_t done;
+    agile_fault fault;
+} agile_req_result;
+
+/* Gather `n` table handles (client i = tables[i]) into a client set on `device`. The tables
+ * stay owned by the caller and must outlive the set; their later changes are picked up by
+ * the next batch. Errors: EINVAL, ENOMEM, EDEVICE. */
+int agile_clients_create(agile_clients** out, agile_rt* const* tables, uint32_t n, int device);
+int agile_clients_destroy(agile_clients* cs);
+
+/* Run `nreq` requests (host array) in one persistent launch on `stream`. d_ptrs holds the
+ * pointer arguments of all requests (device, 16-byte aligned); d_ptr_verdict / d_ptr_owner
+ * (device, one entry per pointer) receive each pointer's verdict and owner; d_result (device,
+ * nreq entries) receives each request's result. The request array is copied before the call
+ * returns. Requests must not write into each other's inputs or outputs. Errors: EINVAL (bad
+ * client index, sizes, alignment), ENOMEM, EDEVICE. */
+int agile_batch_run(agile_clients* cs, const agile_request* reqs, uint32_t nreq,
+                    const agile_ptr* d_ptrs, uint64_t nptrs, uint8_t* d_ptr_verdict,
+                    int32_t* d_ptr_owner, agile_req_result* d_result, void* stream);
+
 /* Static text for a status code. */
 const char* agile_strerror(int code);
 

@@ -1,0 +1,310 @@
+// Batched multi-client requests in one persistent launch.
+//
+// The paper's runtime assigns each client to a worker, and the worker checks every pointer
+// argument of a mediated request against that client's own allocations before the real call
+// (AgileOS Sections IV-B, IV-C, IV-F; a pointer valid for another client is not valid here,
+// Section III). Here one launch serves many requests of many clients: every request is cut
+// into tiles (pointer validation, guarded copy, guarded gather), workgroups pull tiles from an
+// atomic counter until none are left (every workgroup exits once the counter passes the last
+// tile), and the workgroup that finishes a request's last tile writes the request's result:
+// the lowest failing pointer argument and the request's fault record.
+#include "launch.h"
+
+namespace agile {
+
+constexpr int BBLOCK = 256;
+constexpr uint64_t TILE_PTRS = 2048;       // pointers per validation tile (8 per thread)
+constexpr uint64_t TILE_COPY = 1ull << 20; // bytes per copy tile
+constexpr uint64_t TILE_ROWS = 16384;      // rows per gather tile
+constexpr int VQ = 8;
+
+__device__ inline void tiles_of(const BatchReq& q, uint64_t& vt, uint64_t& ct) {
+    vt = (q.nptr + TILE_PTRS - 1) / TILE_PTRS;
+    ct = (q.copy_bytes + TILE_COPY - 1) / TILE_COPY;
+}
+
+// Binding of one pointer by one lane (the finishing workgroup's bookkeeping).
+__device__ inline Bind bind_lane(const DevTable& t, uint64_t p) {
+    Bind r{0, 0};
+    const int64_t b = bucket_search_lane(t, p);
+    if (b < 0) return r;
+    const PairRec rec = load_rec(t.rec + b);
+    const bool second = rec.base1 <= p;
+    const uint64_t end = second ? rec.end1 : rec.end0;
+    const uint32_t meta = second ? rec.meta1 : rec.meta0;
+    if (p < end && (meta & 3u) == KIND_USER) {
+        r.lo = second ? rec.base1 : t.split64[b];
+        r.hi = end;
+    }
+    return r;
+}
+
+// VQ pointer queries per lane, searched together (uniform trip count over the client table).
+__device__ inline void validate_tile(const DevTable& t, const ulonglong2* ptrs, uint64_t p0,
+                                     uint64_t k0, uint64_t k1, uint8_t* pv, int32_t* po,
+                                     uint32_t& minfail) {
+    uint64_t a[VQ], L[VQ];
+    uint32_t base[VQ];
+    bool live[VQ];
+#pragma unroll
+    for (int q = 0; q < VQ; ++q) {
+        const uint64_t k = k0 + (uint64_t)q * BBLOCK + threadIdx.x;
+        live[q] = k < k1;
+        const ulonglong2 x = live[q] ? ptrs[p0 + k] : make_ulonglong2(0, 0);
+        a[q] = x.x;
+        L[q] = x.y < 1 ? 1 : x.y;
+        base[q] = 0;
+    }
+    for (uint32_t len = t.nb; len > 1;) {
+        const uint32_t half = len >> 1;
+#pragma unroll
+        for (int q = 0; q < VQ; ++q)
+            base[q] = t.split64[base[q] + half] <= a[q] ? base[q] + half : base[q];
+        len -= half;
+    }
+#pragma unroll
+    for (int q = 0; q < VQ; ++q) {
+        if (!live[q]) continue;
+        const uint64_t k = k0 + (uint64_t)q * BBLOCK + threadIdx.x;
+        uint8_t v = V_UNMAPPED;
+        int32_t o = -1;
+        if (t.nb > 0 && t.split64[base[q]] <= a[q]) classify_in_bucket(load_rec(t.rec + base[q]), a[q], L[q], v, o);
+        pv[p0 + k] = v;
+        po[p0 + k] = o;
+        if (v != V_ALLOW && (uint32_t)k < minfail) minfail = (uint32_t)k;
+    }
+}
+
+// Bytes [o0, o1) of a guarded copy whose arguments allow the prefixes Ks (src) and Kd (dst).
+__device__ inline void copy_tile(uint8_t* dst, const uint8_t* src, uint64_t o0, uint64_t o1,
+                                 uint64_t Ks, uint64_t Kd) {
+    const uint64_t K = Ks < Kd ? Ks : Kd;
+    const bool vec = (((uint64_t)dst | (uint64_t)src | o0) & 15) == 0;
+    uint64_t done = o0;
+    if (vec) {
+        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+        const uint64_t v0 = o0 / 16, v1 = o1 / 16;
+        for (uint64_t v = v0 + threadIdx.x; v < v1; v += BBLOCK) {
+            const uint64_t b0 = v * 16;
+            if (b0 + 16 <= K) {
+                reinterpret_cast<u32x4*>(dst)[v] = reinterpret_cast<const u32x4*>(src)[v];
+            } else if (b0 >= Ks && b0 + 16 <= Kd) {
+                reinterpret_cast<u32x4*>(dst)[v] = u32x4{0u, 0u, 0u, 0u};
+            } else if (b0 < Kd) {
+                for (uint64_t k = b0; k < b0 + 16; ++k) {
+                    const uint8_t x = k < Ks ? src[k] : (uint8_t)0;
+                    if (k < Kd) dst[k] = x;
+                }
+            }
+        }
+        done = v1 * 16;
+    }
+    for (uint64_t k = done + threadIdx.x; k < o1; k += BBLOCK) {
+        const uint8_t x = k < Ks ? src[k] : (uint8_t)0;
+        if (k < Kd) dst[k] = x;
+    }
+}
+
+__device__ inline void gather_tile(const DevTable& t, const BatchReq& q, uint64_t i0, uint64_t i1,
+                                   FaultAcc& acc) {
+    const uint64_t rb = q.gather_row_bytes, D = rb / 4, n = q.gather_n;
+    const int64_t* idx = reinterpret_cast<const int64_t*>(q.gather_idx);
+    const uint8_t* T = reinterpret_cast<const uint8_t*>(q.gather_table);
+    uint8_t* out = reinterpret_cast<uint8_t*>(q.gather_out);
+    const Bind bi = bind_wave(t, q.gather_idx);
+    const Bind bt = bind_wave(t, q.gather_table);
+    const Bind bo = bind_wave(t, q.gather_out);
+    const uint64_t Ki = clip_prefix(bi, q.gather_idx, n, 8);
+    const uint64_t Ko = clip_prefix(bo, q.gather_out, n * D, 4);
+    const RowGuard g = row_guard(bt, q.gather_table, rb);
+    for (uint64_t i = i0 + threadIdx.x; i < i1; i += BBLOCK) {
+        const bool iok = i < Ki;
+        const int64_t iv = iok ? idx[i] : 0;
+        if (!iok) acc.note((i * D) << 2);
+        const bool full = g.rlo <= iv && iv <= g.rhi;
+        const uint8_t* trow = T + (uint64_t)iv * rb;
+        for (uint64_t col = 0; col < D; ++col) {
+            const uint64_t e = i * D + col;
+            uint32_t val = 0;
+            if (full || elem_ok(g, iv, rb, col, 4)) val = *reinterpret_cast<const uint32_t*>(trow + col * 4);
+            else acc.note((e << 2) | 1u);
+            if (e < Ko) *reinterpret_cast<uint32_t*>(out + e * 4) = val;
+            else acc.note((e << 2) | 2u);
+        }
+    }
+}
+
+// Result of request r, written by the workgroup that finished its last tile (one thread).
+__device__ inline void finish_request(const BatchArgs& A, uint32_t r) {
+    const BatchReq& q = A.reqs[r];
+    const DevTable& t = A.tables[q.client];
+    BatchScratch* s = A.scratch + r;
+    agile_req_result_dev* res = A.result + r;
+    const uint32_t mf = atomicAdd(&s->minfail, 0u);
+    if (mf != 0xFFFFFFFFu) {
+        res->verdict = A.pv[q.ptr_off + mf];
+        res->arg = (int32_t)mf;
+        res->owner = A.po[q.ptr_off + mf];
+    } else {
+        res->verdict = V_ALLOW;
+        res->arg = -1;
+        res->owner = -1;
+    }
+    DevLog f{};
+    f.first_seq = ~0ull;
+    f.first_owner = -1;
+    if (q.copy_bytes) {
+        const uint64_t n = q.copy_bytes;
+        const uint64_t Ks = clip_prefix(bind_lane(t, q.copy_src), q.copy_src, n, 1);
+        const uint64_t Kd = clip_prefix(bind_lane(t, q.copy_dst), q.copy_dst, n, 1);
+        const uint64_t cnt = (n - Ks) + (n - Kd);
+        if (cnt) {
+            f.count += cnt;
+            const uint32_t operand = Ks <= Kd ? 0u : 1u;
+            const uint64_t k = operand ? Kd : Ks;
+            const uint64_t Aaddr = (operand ? q.copy_dst : q.copy_src) + k;
+            uint32_t v;
+            int32_t o;
+            reason_lane(t, Aaddr, 1, v, o);
+            f.first_seq = r;
+            f.first_elem = k;
+            f.first_addr = Aaddr;
+            f.first_width = 1;
+            f.first_op = 1;
+            f.first_operand = operand;
+            f.first_verdict = v;
+            f.first_owner = o;
+        }
+    }
+    const unsigned long long gc = atomicAdd(&s->gcount, 0ull);
+    if (gc) {
+        f.count += gc;
+        if (f.first_seq == ~0ull) {
+            const unsigned long long key = atomicMin(&s->gminkey, ~0ull);
+            const uint64_t D = q.gather_row_bytes / 4;
+            const unsigned long long elem = key >> 2;
+            const uint32_t operand = (uint32_t)(key & 3u);
+            const uint64_t i = elem / D, col = elem % D;
+            __int128 Aa;
+            uint32_t w = 4;
+            if (operand == 0) {
+                Aa = (__int128)q.gather_idx + (__int128)(8 * i);
+                w = 8;
+            } else if (operand == 1) {
+                const uint64_t Ki = clip_prefix(bind_lane(t, q.gather_idx), q.gather_idx, q.gather_n, 8);
+                const int64_t v = i < Ki ? reinterpret_cast<const int64_t*>(q.gather_idx)[i] : 0;
+                Aa = (__int128)q.gather_table + (__int128)v * (__int128)q.gather_row_bytes +
+                     (__int128)(col * 4);
+            } else {
+                Aa = (__int128)q.gather_out + (__int128)elem * 4;
+            }
+            uint32_t v = V_UNMAPPED;
+            int32_t o = -1;
+            if (Aa >= 0 && Aa <= (__int128)U64MAX) reason_lane(t, (uint64_t)Aa, w, v, o);
+            f.first_seq = r;
+            f.first_elem = elem;
+            f.first_addr = (uint64_t)Aa;
+            f.first_width = w;
+            f.first_op = 3;
+            f.first_operand = operand;
+            f.first_verdict = v;
+            f.first_owner = o;
+        }
+    }
+    res->fault_count = f.count;
+    res->fault_seq = f.first_seq;
+    res->fault_elem = f.first_elem;
+    res->fault_addr = f.first_addr;
+    res->fault_width = f.first_width;
+    res->fault_op = f.first_op;
+    res->fault_operand = f.first_operand;
+    res->fault_verdict = f.first_verdict;
+    res->fault_owner = f.first_owner;
+    res->fault_reserved = 0;
+    __threadfence();
+    res->done = 1;
+}
+
+__global__ __launch_bounds__(BBLOCK) void k_batch(BatchArgs A) {
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_minfail;
+    const uint32_t tid = threadIdx.x;
+    while (true) {
+        if (tid == 0) {
+            s_tile = atomicAdd(&A.ctl->next, 1u);
+            s_minfail = 0xFFFFFFFFu;
+        }
+        __syncthreads();
+        const uint64_t tile = s_tile;
+        if (tile >= A.ntiles) break;  // uniform: every wave of the block leaves together
+        // request owning this tile: last r with tstart[r] <= tile
+        uint32_t lo = 0, len = A.nreq;
+        while (len > 1) {
+            const uint32_t half = len >> 1;
+            lo = A.tstart[lo + half] <= tile ? lo + half : lo;
+            len -= half;
+        }
+        const uint32_t r = lo;
+        const BatchReq q = A.reqs[r];
+        const DevTable& t = A.tables[q.client];
+        uint64_t vt, ct;
+        tiles_of(q, vt, ct);
+        const uint64_t local = tile - A.tstart[r];
+        if (local < vt) {
+            const uint64_t k0 = local * TILE_PTRS;
+            const uint64_t k1 = k0 + TILE_PTRS < q.nptr ? k0 + TILE_PTRS : q.nptr;
+            uint32_t mf = 0xFFFFFFFFu;
+            validate_tile(t, A.ptrs, q.ptr_off, k0, k1, A.pv, A.po, mf);
+            atomicMin(&s_minfail, mf);
+            __syncthreads();
+            if (tid == 0 && s_minfail != 0xFFFFFFFFu) atomicMin(&A.scratch[r].minfail, s_minfail);
+        } else if (local < vt + ct) {
+            const uint64_t o0 = (local - vt) * TILE_COPY;
+            const uint64_t o1 = o0 + TILE_COPY < q.copy_bytes ? o0 + TILE_COPY : q.copy_bytes;
+            const Bind bs = bind_wave(t, q.copy_src);
+            const Bind bd = bind_wave(t, q.copy_dst);
+            const uint64_t Ks = clip_prefix(bs, q.copy_src, q.copy_bytes, 1);
+            const uint64_t Kd = clip_prefix(bd, q.copy_dst, q.copy_bytes, 1);
+            copy_tile(reinterpret_cast<uint8_t*>(q.copy_dst), reinterpret_cast<const uint8_t*>(q.copy_src),
+                      o0, o1, Ks, Kd);
+        } else if (q.gather_n) {
+            const uint64_t i0 = (local - vt - ct) * TILE_ROWS;
+            const uint64_t i1 = i0 + TILE_ROWS < q.gather_n ? i0 + TILE_ROWS : q.gather_n;
+            FaultAcc acc;
+            gather_tile(t, q, i0, i1, acc);
+            const unsigned long long c = wave_sum_u64(acc.cnt);
+            const unsigned long long m = wave_min_u64(acc.mk);
+            if ((tid & 63u) == 0 && c) {
+                atomicAdd(&A.scratch[r].gcount, c);
+                atomicMin(&A.scratch[r].gminkey, m);
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            __threadfence();
+            if (atomicSub(&A.scratch[r].remaining, 1u) == 1u) {
+                __threadfence();
+                finish_request(A, r);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_batch(const BatchArgs& A, const DevInfo& d, hipStream_t s) {
+    if (A.ntiles == 0) return hipSuccess;
+    uint64_t grid = (uint64_t)d.num_cu * 4;
+    if (grid > A.ntiles) grid = A.ntiles;
+    hipLaunchKernelGGL(k_batch, dim3((uint32_t)grid), dim3(BBLOCK), 0, s, A);
+    return hipGetLastError();
+}
+
+uint64_t batch_tiles(const BatchReq& q) {
+    const uint64_t vt = (q.nptr + TILE_PTRS - 1) / TILE_PTRS;
+    const uint64_t ct = (q.copy_bytes + TILE_COPY - 1) / TILE_COPY;
+    const uint64_t gt = (q.gather_n + TILE_ROWS - 1) / TILE_ROWS;
+    const uint64_t all = vt + ct + gt;
+    return all ? all : 1;
+}
+
+}  // namespace agile

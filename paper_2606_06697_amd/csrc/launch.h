@@ -42,4 +42,59 @@ hipError_t launch_scatter_add(bool guard, const DevTable& t, DevLog* log, void* 
 
 hipError_t launch_log_reset(DevLog* log, hipStream_t s);
 
+// ---- batched multi-client launch (device images of the public request/result layouts) ----
+struct BatchReq {
+    uint32_t client, reserved0;
+    uint64_t ptr_off, nptr;
+    uint64_t copy_dst, copy_src, copy_bytes;
+    uint64_t gather_out, gather_table, gather_idx, gather_n;
+    uint32_t gather_row_bytes, reserved1;
+    uint64_t reserved2;
+};
+static_assert(sizeof(BatchReq) == 96, "BatchReq mirrors agile_request");
+
+struct BatchScratch {
+    unsigned int minfail;      // lowest failing pointer index of the request (or ~0)
+    unsigned int remaining;    // tiles of the request not finished yet
+    unsigned long long gcount; // gather denials
+    unsigned long long gminkey;
+    unsigned long long pad;
+};
+static_assert(sizeof(BatchScratch) == 32, "BatchScratch is 32 bytes");
+
+struct BatchCtl {
+    unsigned int next;  // next tile to hand out
+    unsigned int pad[15];
+};
+
+struct agile_req_result_dev {
+    uint32_t verdict;
+    int32_t arg;
+    int32_t owner;
+    uint32_t done;
+    unsigned long long fault_count, fault_seq, fault_elem, fault_addr;
+    uint32_t fault_width, fault_op, fault_operand, fault_verdict;
+    int32_t fault_owner;
+    uint32_t fault_reserved;
+};
+static_assert(sizeof(agile_req_result_dev) == 72, "mirrors agile_req_result");
+
+struct BatchArgs {
+    BatchCtl* ctl;
+    const uint64_t* tstart;  // nreq + 1 entries: first tile of each request, then the total
+    const BatchReq* reqs;
+    BatchScratch* scratch;
+    const DevTable* tables;
+    const ulonglong2* ptrs;
+    uint8_t* pv;
+    int32_t* po;
+    agile_req_result_dev* result;
+    uint64_t ntiles;
+    uint32_t nreq;
+    uint32_t pad;
+};
+
+uint64_t batch_tiles(const BatchReq& q);
+hipError_t launch_batch(const BatchArgs& a, const DevInfo& d, hipStream_t s);
+
 }  // namespace agile

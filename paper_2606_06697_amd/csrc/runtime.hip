@@ -596,6 +596,159 @@ int agile_fault_log_read(agile_rt* rt, agile_fault* out, int clear, void* stream
     return out->count ? AGILE_EFAULTED : AGILE_OK;
 }
 
+// ---- batched multi-client requests -----------------------------------------------------
+namespace {
+constexpr int BATCH_SLOTS = 4;
+struct BatchSlot {
+    void* dmem = nullptr;
+    size_t dcap = 0;
+    void* hstage = nullptr;
+    size_t hcap = 0;
+    hipEvent_t done = nullptr;
+    bool used = false;
+};
+size_t align64(size_t x) { return (x + 63) & ~(size_t)63; }
+}  // namespace
+
+struct agile_clients {
+    int device = 0;
+    std::vector<agile_rt*> tables;
+    BatchSlot slot[BATCH_SLOTS];
+    int next = 0;
+};
+
+int agile_clients_create(agile_clients** out, agile_rt* const* tables, uint32_t n, int device) {
+    if (!out || !tables || n == 0) return AGILE_EINVAL;
+    for (uint32_t i = 0; i < n; ++i)
+        if (!tables[i] || tables[i]->device != device) return AGILE_EINVAL;
+    DeviceGuard dg(device);
+    if (!dg.ok) return AGILE_EDEVICE;
+    agile_clients* cs = new (std::nothrow) agile_clients();
+    if (!cs) return AGILE_ENOMEM;
+    cs->device = device;
+    cs->tables.assign(tables, tables + n);
+    for (auto& sl : cs->slot) {
+        if (hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
+            agile_clients_destroy(cs);
+            return AGILE_EDEVICE;
+        }
+    }
+    *out = cs;
+    return AGILE_OK;
+}
+
+int agile_clients_destroy(agile_clients* cs) {
+    if (!cs) return AGILE_OK;
+    DeviceGuard dg(cs->device);
+    int rc = AGILE_OK;
+    for (auto& sl : cs->slot) {
+        if (sl.done) {
+            if (sl.used && hipEventSynchronize(sl.done) != hipSuccess) rc = AGILE_EDEVICE;
+            (void)hipEventDestroy(sl.done);
+        }
+        if (sl.dmem) (void)hipFree(sl.dmem);
+        if (sl.hstage) (void)hipHostFree(sl.hstage);
+    }
+    delete cs;
+    return rc;
+}
+
+int agile_batch_run(agile_clients* cs, const agile_request* reqs, uint32_t nreq,
+                    const agile_ptr* d_ptrs, uint64_t nptrs, uint8_t* d_ptr_verdict,
+                    int32_t* d_ptr_owner, agile_req_result* d_result, void* stream) {
+    static_assert(sizeof(agile_request) == sizeof(BatchReq), "request layout");
+    static_assert(sizeof(agile_req_result) == sizeof(agile_req_result_dev), "result layout");
+    if (!cs) return AGILE_EINVAL;
+    if (nreq == 0) return AGILE_OK;
+    if (!reqs || !d_result) return AGILE_EINVAL;
+    if (nptrs && (!d_ptrs || !d_ptr_verdict || !d_ptr_owner || ((uint64_t)d_ptrs & 15)))
+        return AGILE_EINVAL;
+    const uint32_t ncl = (uint32_t)cs->tables.size();
+    uint64_t ntiles = 0;
+    for (uint32_t r = 0; r < nreq; ++r) {
+        const agile_request& q = reqs[r];
+        if (q.client >= ncl || q.ptr_off > nptrs || q.nptr > nptrs - q.ptr_off) return AGILE_EINVAL;
+        if (q.nptr > 0xFFFFFFFEull) return AGILE_EINVAL;
+        if (q.gather_n && (q.gather_row_bytes == 0 || q.gather_row_bytes % 4 ||
+                           ((q.gather_out | q.gather_table) & 3) || (q.gather_idx & 7) ||
+                           q.gather_n > ((1ull << 62) - 1) / (q.gather_row_bytes / 4)))
+            return AGILE_EINVAL;
+        ntiles += batch_tiles(reinterpret_cast<const BatchReq&>(q));
+    }
+    DeviceGuard dg(cs->device);
+    if (!dg.ok) return AGILE_EDEVICE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (agile_rt* rt : cs->tables) {
+        const int rc = prepare(rt, s);
+        if (rc != AGILE_OK) return rc;
+    }
+    // layout: ctl | tstart[nreq+1] | reqs | scratch | tables
+    const size_t o_ts = align64(sizeof(BatchCtl));
+    const size_t o_rq = o_ts + align64((size_t)(nreq + 1) * 8);
+    const size_t o_sc = o_rq + align64((size_t)nreq * sizeof(BatchReq));
+    const size_t o_tb = o_sc + align64((size_t)nreq * sizeof(BatchScratch));
+    const size_t bytes = o_tb + align64((size_t)ncl * sizeof(DevTable));
+    BatchSlot& sl = cs->slot[cs->next];
+    cs->next = (cs->next + 1) % BATCH_SLOTS;
+    if (sl.used) {
+        if (hipEventSynchronize(sl.done) != hipSuccess) return AGILE_EDEVICE;
+        sl.used = false;
+    }
+    if (sl.dcap < bytes) {
+        if (sl.dmem) (void)hipFree(sl.dmem);
+        if (sl.hstage) (void)hipHostFree(sl.hstage);
+        sl.dmem = sl.hstage = nullptr;
+        sl.dcap = sl.hcap = 0;
+        const size_t cap = bytes * 2;
+        if (hipMalloc(&sl.dmem, cap) != hipSuccess) return AGILE_ENOMEM;
+        if (hipHostMalloc(&sl.hstage, cap, hipHostMallocDefault) != hipSuccess) {
+            (void)hipFree(sl.dmem);
+            sl.dmem = nullptr;
+            return AGILE_ENOMEM;
+        }
+        sl.dcap = sl.hcap = cap;
+    }
+    uint8_t* h = static_cast<uint8_t*>(sl.hstage);
+    std::memset(h, 0, o_ts);
+    uint64_t* ts = reinterpret_cast<uint64_t*>(h + o_ts);
+    BatchReq* rq = reinterpret_cast<BatchReq*>(h + o_rq);
+    BatchScratch* sc = reinterpret_cast<BatchScratch*>(h + o_sc);
+    DevTable* tb = reinterpret_cast<DevTable*>(h + o_tb);
+    uint64_t acc = 0;
+    for (uint32_t r = 0; r < nreq; ++r) {
+        std::memcpy(&rq[r], &reqs[r], sizeof(BatchReq));
+        const uint64_t k = batch_tiles(rq[r]);
+        ts[r] = acc;
+        acc += k;
+        sc[r].minfail = 0xFFFFFFFFu;
+        sc[r].remaining = (unsigned int)k;
+        sc[r].gcount = 0;
+        sc[r].gminkey = ~0ull;
+        sc[r].pad = 0;
+    }
+    ts[nreq] = acc;
+    for (uint32_t c = 0; c < ncl; ++c) tb[c] = cs->tables[c]->tab;
+    if (hipMemcpyAsync(sl.dmem, h, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+        return AGILE_EDEVICE;
+    uint8_t* d = static_cast<uint8_t*>(sl.dmem);
+    BatchArgs A{};
+    A.ctl = reinterpret_cast<BatchCtl*>(d);
+    A.tstart = reinterpret_cast<const uint64_t*>(d + o_ts);
+    A.reqs = reinterpret_cast<const BatchReq*>(d + o_rq);
+    A.scratch = reinterpret_cast<BatchScratch*>(d + o_sc);
+    A.tables = reinterpret_cast<const DevTable*>(d + o_tb);
+    A.ptrs = reinterpret_cast<const ulonglong2*>(d_ptrs);
+    A.pv = d_ptr_verdict;
+    A.po = d_ptr_owner;
+    A.result = reinterpret_cast<agile_req_result_dev*>(d_result);
+    A.ntiles = ntiles;
+    A.nreq = nreq;
+    if (launch_batch(A, cs->tables[0]->info, s) != hipSuccess) return AGILE_EDEVICE;
+    if (hipEventRecord(sl.done, s) != hipSuccess) return AGILE_EDEVICE;
+    sl.used = true;
+    return AGILE_OK;
+}
+
 // ---- unguarded twins ------------------------------------------------------------------
 static DevInfo current_info() {
     static thread_local int cached_dev = -1;

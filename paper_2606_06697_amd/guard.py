@@ -11,6 +11,7 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -65,7 +66,23 @@ _SIGS = {
     "agile_unguarded_triad": (_int, [_vp, _vp, _vp, ctypes.c_float, _u64, _vp]),
     "agile_unguarded_gather": (_int, [_vp, _vp, _u64, _vp, _u64, _int, _vp]),
     "agile_unguarded_scatter": (_int, [_vp, _u64, _vp, _vp, _u64, _int, _int, _vp]),
+    "agile_clients_create": (_int, [ctypes.POINTER(_vp), _vp, _u32, _int]),
+    "agile_clients_destroy": (_int, [_vp]),
+    "agile_batch_run": (_int, [_vp, _vp, _u32, _vp, _u64, _vp, _vp, _vp, _vp]),
 }
+
+# numpy mirrors of agile_request (96 bytes) and agile_req_result (72 bytes)
+REQUEST_DTYPE = np.dtype([
+    ("client", "<u4"), ("reserved0", "<u4"), ("ptr_off", "<u8"), ("nptr", "<u8"),
+    ("copy_dst", "<u8"), ("copy_src", "<u8"), ("copy_bytes", "<u8"), ("gather_out", "<u8"),
+    ("gather_table", "<u8"), ("gather_idx", "<u8"), ("gather_n", "<u8"),
+    ("gather_row_bytes", "<u4"), ("reserved1", "<u4"), ("reserved2", "<u8")])
+RESULT_DTYPE = np.dtype([
+    ("verdict", "<u4"), ("arg", "<i4"), ("owner", "<i4"), ("done", "<u4"), ("count", "<u8"),
+    ("first_seq", "<u8"), ("first_elem", "<u8"), ("first_addr", "<u8"),
+    ("first_width", "<u4"), ("first_op", "<u4"), ("first_operand", "<u4"),
+    ("first_verdict", "<u4"), ("first_owner", "<i4"), ("reserved", "<u4")])
+assert REQUEST_DTYPE.itemsize == 96 and RESULT_DTYPE.itemsize == 72
 
 _lib = None
 
@@ -216,6 +233,35 @@ def agile_unguarded_scatter(dst, row_bytes: int, idx, src, n: int, dtype: int = 
                             accumulate: int = 0, stream=None) -> None:
     _check(lib().agile_unguarded_scatter(_ptr(dst), row_bytes, _ptr(idx), _ptr(src), n, dtype,
                                          accumulate, _stream(stream)), "agile_unguarded_scatter")
+
+
+def agile_clients_create(tables, device: int = 0) -> int:
+    """Client set from table handles (ints) or RangeTable objects, client i = tables[i]."""
+    hs = [t.handle if isinstance(t, RangeTable) else int(t) for t in tables]
+    arr = (_vp * len(hs))(*hs)
+    h = _vp()
+    _check(lib().agile_clients_create(ctypes.byref(h), arr, len(hs), device),
+           "agile_clients_create")
+    return h.value
+
+
+def agile_clients_destroy(cs: int) -> None:
+    _check(lib().agile_clients_destroy(cs), "agile_clients_destroy")
+
+
+def agile_batch_run(cs: int, reqs: np.ndarray, ptrs, nptrs: int, ptr_verdict, ptr_owner, result,
+                    stream=None) -> None:
+    """reqs: numpy array of REQUEST_DTYPE (host); ptrs: device int64 [nptrs, 2]; ptr_verdict
+    (uint8) / ptr_owner (int32): device [nptrs]; result: device buffer of len(reqs) * 72 bytes."""
+    reqs = np.ascontiguousarray(reqs, dtype=REQUEST_DTYPE)
+    _check(lib().agile_batch_run(cs, reqs.ctypes.data, len(reqs), _ptr(ptrs), nptrs,
+                                 _ptr(ptr_verdict), _ptr(ptr_owner), _ptr(result),
+                                 _stream(stream)), "agile_batch_run")
+
+
+def batch_results(result: torch.Tensor, nreq: int) -> np.ndarray:
+    """Copy a device result buffer to host as a RESULT_DTYPE array (synchronizes)."""
+    return result[:nreq * RESULT_DTYPE.itemsize].cpu().numpy().view(RESULT_DTYPE).copy()
 
 
 class RangeTable:

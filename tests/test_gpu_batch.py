@@ -1,0 +1,175 @@
+"""Batched multi-client requests (one persistent launch) against the oracle.
+
+Four clients, each with its own table (synthetic ranges plus a real device arena holding a
+copy source, a protected canary, a hole, a gather table, an index buffer and one output slot
+per request). Requests mix pointer validation (own-table, cross-client and hostile pointers)
+with guarded copies or gathers, several of them hostile. Checked: every pointer's verdict and
+owner, every request's lowest failing argument, the arenas byte for byte, every request's fault
+record; then each request run alone gives the same result as in the mix.
+"""
+import random
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import need_gpu, guard_mod
+from oracle import guarded as G
+from oracle.batched import batch_verdicts
+from oracle.memory import Memory
+from oracle.table import RangeTable as OracleTable
+from synth import make_table, make_queries
+
+pytestmark = pytest.mark.gpu
+
+ARENA = 1 << 20
+SRC, PROT, HOLE, GT, IDX, SLOTS = 0, 128 << 10, 132 << 10, 136 << 10, 392 << 10, 520 << 10
+SLOT = 16 << 10
+NSLOT = (ARENA - SLOTS) // SLOT
+
+
+class Client:
+    def __init__(self, g, c):
+        self.tb = make_table(200, 40, 100 + c, first_hi=2**44)
+        self.rt = g.RangeTable(512)
+        self.ot = OracleTable()
+        self.rt.insert_many(self.tb.base, self.tb.size, self.tb.kind)
+        for b, s, k in zip(self.tb.base.tolist(), self.tb.size.tolist(), self.tb.kind.tolist()):
+            self.ot.insert(b, s, k)
+        gen = torch.Generator().manual_seed(1000 + c)
+        host = torch.randint(0, 256, (ARENA,), dtype=torch.uint8, generator=gen)
+        rows = (IDX - GT) // 4
+        idx = torch.randint(0, rows, ((SLOTS - IDX) // 8,), generator=gen)
+        bad = torch.randperm(idx.numel(), generator=gen)[:idx.numel() // 20]
+        idx[bad] = torch.tensor([rows, rows + 7, -1, -(1 << 40), (PROT - GT) // 4 + 3, 1 << 62],
+                                dtype=torch.int64)[torch.arange(bad.numel()) % 6]
+        host[IDX:SLOTS] = idx.view(torch.uint8)
+        self.dev = host.cuda()
+        self.base = self.dev.data_ptr()
+        self.mem = Memory()
+        self.mem.add(self.base, host.numpy())
+        regions = [(SRC, PROT, 0), (PROT, HOLE, 1), (GT, IDX, 0), (IDX, SLOTS, 0)]
+        regions += [(SLOTS + k * SLOT, SLOTS + (k + 1) * SLOT, 0) for k in range(NSLOT)]
+        for lo, hi, kind in regions:
+            a = self.rt.insert(self.base + lo, hi - lo, kind)
+            b = self.ot.insert(self.base + lo, hi - lo, kind)
+            assert a == b
+
+    def a(self, off):
+        return self.base + off
+
+
+def build(seed, ncl=4, nreq=40):
+    g = guard_mod()
+    cls = [Client(g, c) for c in range(ncl)]
+    rng = random.Random(seed)
+    reqs = np.zeros(nreq, dtype=g.REQUEST_DTYPE)
+    ptrs = []
+    slot_of = {c: 0 for c in range(ncl)}
+    for r in range(nreq):
+        c = r % ncl
+        cl = cls[c]
+        other = cls[(c + 1) % ncl]
+        m = rng.choice([0, 1, 3, 50, 700, 3000])
+        q = make_queries(cl.tb, max(m, 1), seed * 1000 + r).numpy()[:m].tolist()
+        for k in range(len(q)):
+            u = rng.random()
+            if u < 0.1:
+                q[k] = [cl.a(SLOTS + rng.randrange(0, SLOT)), rng.choice([1, 8, 64])]
+            elif u < 0.15:
+                q[k] = [other.a(SRC + 64), 16]                # valid only for another client
+            elif u < 0.18:
+                q[k] = [cl.a(PROT + 8), 8]
+        reqs[r]["client"] = c
+        reqs[r]["ptr_off"] = len(ptrs)
+        reqs[r]["nptr"] = len(q)
+        ptrs += q
+        slot = SLOTS + slot_of[c] * SLOT
+        slot_of[c] += 1
+        kind = rng.random()
+        if kind < 0.6:
+            reqs[r]["copy_dst"] = cl.a(slot) if rng.random() < 0.85 else cl.a(HOLE)
+            src = rng.choice([cl.a(SRC + rng.randrange(0, 4096)), cl.a(SRC + 120 * 1024),
+                              cl.a(PROT), other.a(SRC), cl.a(SRC + 3)])
+            reqs[r]["copy_src"] = src
+            reqs[r]["copy_bytes"] = rng.choice([1, 15, 4096, 12345, SLOT, SLOT + 100])
+        elif kind < 0.9:
+            rbytes = rng.choice([4, 8])
+            n = rng.choice([1, 100, 2000, SLOT // rbytes, SLOT // rbytes + 3])
+            reqs[r]["gather_out"] = cl.a(slot)
+            reqs[r]["gather_table"] = cl.a(GT)
+            reqs[r]["gather_idx"] = cl.a(IDX + 8 * rng.randrange(0, 1000))
+            reqs[r]["gather_n"] = n
+            reqs[r]["gather_row_bytes"] = rbytes
+    P = torch.tensor(np.array(ptrs, dtype=np.uint64).reshape(-1, 2).view(np.int64)).cuda() \
+        if ptrs else torch.zeros((1, 2), dtype=torch.int64, device="cuda")
+    return g, cls, reqs, P, len(ptrs)
+
+
+def run_batch(g, cs, reqs, P, nptrs):
+    pv = torch.full((max(nptrs, 1),), 255, dtype=torch.uint8, device="cuda")
+    po = torch.full((max(nptrs, 1),), -7, dtype=torch.int32, device="cuda")
+    res = torch.zeros(len(reqs) * g.RESULT_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    g.agile_batch_run(cs, reqs, P, nptrs, pv, po, res)
+    torch.cuda.synchronize()
+    return pv.cpu().numpy()[:nptrs], po.cpu().numpy()[:nptrs], g.batch_results(res, len(reqs))
+
+
+def oracle_request(cl, q, r):
+    log = G.FaultLog()
+    if q["copy_bytes"]:
+        G.copy_vec(cl.ot, cl.mem, log, r, int(q["copy_dst"]), int(q["copy_src"]),
+                   int(q["copy_bytes"]))
+    if q["gather_n"]:
+        G.gather_vec(cl.ot, cl.mem, log, r, int(q["gather_out"]), int(q["gather_table"]),
+                     int(q["gather_row_bytes"]), int(q["gather_idx"]), int(q["gather_n"]), 4)
+    return log
+
+
+def check_fault(res, log, r, seq):
+    assert res["count"] == log.count, (r, res, log.count)
+    if log.count == 0:
+        assert res["first_seq"] == (1 << 64) - 1
+        return
+    f = log.first
+    got = dict(elem=int(res["first_elem"]), operand=int(res["first_operand"]),
+               addr=int(res["first_addr"]), width=int(res["first_width"]),
+               verdict=int(res["first_verdict"]), owner=int(res["first_owner"]),
+               op=int(res["first_op"]))
+    want = {k: f[k] for k in got}
+    assert got == want and int(res["first_seq"]) == seq, (r, got, want)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_batch_against_oracle_and_alone_identity(seed):
+    need_gpu()
+    g, cls, reqs, P, nptrs = build(seed)
+    cs = g.agile_clients_create([cl.rt for cl in cls])
+    pv, po, res = run_batch(g, cs, reqs, P, nptrs)
+    # pointer verdicts and per-request lowest failing argument
+    ev, eo, rv, ra, ro = batch_verdicts([cl.ot for cl in cls], reqs["client"],
+                                        np.append(reqs["ptr_off"], nptrs).astype(np.int64),
+                                        P.cpu().numpy()[:nptrs].view(np.uint64))
+    assert np.array_equal(pv, ev) and np.array_equal(po, eo)
+    assert np.array_equal(res["verdict"], rv) and np.array_equal(res["arg"], ra)
+    assert np.array_equal(res["owner"], ro) and (res["done"] == 1).all()
+    # data movement and fault records, request by request in the oracle
+    for r, q in enumerate(reqs):
+        log = oracle_request(cls[int(q["client"])], q, r)
+        check_fault(res[r], log, r, r)
+    for c, cl in enumerate(cls):
+        got = cl.dev.cpu().numpy()
+        assert np.array_equal(got, cl.mem.buffer(cl.base)), f"client {c} arena differs"
+        assert (got[PROT:HOLE] == cl.mem.buffer(cl.base)[PROT:HOLE]).all()
+    # each request alone equals its result in the mix (outputs rewritten with the same bytes)
+    for r in range(len(reqs)):
+        one = reqs[r:r + 1].copy()
+        p1, o1, r1 = run_batch(g, cs, one, P, nptrs)
+        a, b = int(reqs[r]["ptr_off"]), int(reqs[r]["ptr_off"] + reqs[r]["nptr"])
+        assert np.array_equal(p1[a:b], pv[a:b]) and np.array_equal(o1[a:b], po[a:b])
+        for k in ("verdict", "arg", "owner", "count", "first_elem", "first_operand",
+                  "first_addr", "first_verdict", "first_owner"):
+            assert r1[0][k] == res[r][k], (r, k)
+    for c, cl in enumerate(cls):
+        assert np.array_equal(cl.dev.cpu().numpy(), cl.mem.buffer(cl.base))
+    g.agile_clients_destroy(cs)
