@@ -41,6 +41,10 @@ def parse():
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-extras", action="store_true",
+                   help="skip the embedding and batched-launch measurements")
+    p.add_argument("--serve-seconds", type=float, default=5.0,
+                   help="length of the serving-loop run (0 skips it)")
     p.add_argument("--queries-log2", type=int, default=28, help=argparse.SUPPRESS)
     return p.parse_args()
 
@@ -138,21 +142,27 @@ def main():
     elapsed = time.perf_counter() - t0
     ms_step = elapsed * 1e3 / args.steps
 
-    # unguarded twins on the same inputs (the hostile indices stay inside the allocation)
-    ug = {"triad": [], "gather": []}
+    # guarded vs unguarded twins on the same inputs, timed the same way (one launch between
+    # two events, interleaved); the hostile indices stay inside the gather buffer
+    twin = {"triad": [], "triad_unguarded": [], "gather": [], "gather_unguarded": []}
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    for name, fn in (("triad", lambda: g.agile_unguarded_triad(a_ref, b, c, 3.0, TRIAD_N)),
-                     ("gather", lambda: g.agile_unguarded_gather(out_ref, table, 4, idx,
-                                                                 GATHER_N))):
-        for _ in range(args.warmup):
-            fn()
-        for _ in range(args.steps):
+    calls = {
+        "triad": lambda: g.agile_guarded_triad(dt.handle, a, b, c, 3.0, TRIAD_N),
+        "triad_unguarded": lambda: g.agile_unguarded_triad(a_ref, b, c, 3.0, TRIAD_N),
+        "gather": lambda: g.agile_guarded_gather(dt.handle, out, table, 4, idx, GATHER_N),
+        "gather_unguarded": lambda: g.agile_unguarded_gather(out_ref, table, 4, idx, GATHER_N),
+    }
+    for rep in range(args.warmup + args.steps):
+        for name, fn in calls.items():
             e0.record()
             fn()
             e1.record()
             e1.synchronize()
-            ug[name].append(e0.elapsed_time(e1))
+            if rep >= args.warmup:
+                twin[name].append(e0.elapsed_time(e1))
+    dt.fault_log(clear=True)
     torch.cuda.synchronize()
+    ug = {"triad": twin["triad_unguarded"], "gather": twin["gather_unguarded"]}
     ok_triad = torch.equal(a.view(torch.int32), a_ref.view(torch.int32))
     good = (idx >= 0) & (idx < GATHER_ROWS)
     ok_gather = bool(torch.equal(out[good], out_ref[good])) and bool((out[~good] == 0).all())
@@ -163,6 +173,8 @@ def main():
     t_v, t_t, t_g = med(t_kern["validate"]), med(t_kern["triad"]), med(t_kern["gather"])
     gbs = {"validate": bytes_validate / t_v / 1e6, "triad": bytes_triad / t_t / 1e6,
            "gather": bytes_gather / t_g / 1e6}
+    tw_t, tw_g = med(twin["triad"]), med(twin["gather"])
+    gbs_twin = {"triad": bytes_triad / tw_t / 1e6, "gather": bytes_gather / tw_g / 1e6}
     ug_t, ug_g = med(ug["triad"]), med(ug["gather"])
     ugbs = {"triad": bytes_triad / ug_t / 1e6, "gather": bytes_gather / ug_g / 1e6}
     dominant = max(("validate", t_v), ("triad", t_t), ("gather", t_g), key=lambda x: x[1])[0]
@@ -199,8 +211,9 @@ def main():
                       "gather_unguarded": round(ug_g, 4)},
         "guarded_gbps": {k: round(v, 1) for k, v in gbs.items()},
         "unguarded_gbps": {k: round(v, 1) for k, v in ugbs.items()},
-        "guarded_over_unguarded": {k: round(gbs[k] / ugbs[k], 4) for k in ugbs},
-        "overhead_pct": {k: round(100.0 * (ugbs[k] / gbs[k] - 1.0), 2) for k in ugbs},
+        "guarded_gbps_isolated": {k: round(v, 1) for k, v in gbs_twin.items()},
+        "guarded_over_unguarded": {k: round(gbs_twin[k] / ugbs[k], 4) for k in ugbs},
+        "overhead_pct": {k: round(100.0 * (ugbs[k] / gbs_twin[k] - 1.0), 2) for k in ugbs},
         "unguarded_frac_of_peak": {k: round(v / PEAK_HBM_GBS, 4) for k, v in ugbs.items()},
         "faults_per_step": n_bad,
         "twin_results_equal": {"triad": ok_triad, "gather": ok_gather},
@@ -211,9 +224,208 @@ def main():
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
                      "bytes_per_launch": per_launch[dominant]},
     }
+    result["roofline"]["traffic"] = measured_traffic(dominant, per_launch[dominant])
+    del q, verdict, owner, a, b, c, a_ref, gbuf, table, idx, out, out_ref
+    vt.close()
+    dt.close()
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        result["embedding"] = bench_embedding(g, args)
+        torch.cuda.empty_cache()
+        result["batch"] = bench_batch(g, args)
+        torch.cuda.empty_cache()
+    if args.serve_seconds > 0:
+        srv = bench_serving(g, args)
+        result["serving"] = srv
+        result["latency_p50_ms"] = srv["latency_p50_ms"]
+        result["latency_p99_ms"] = srv["latency_p99_ms"]
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(tb, step_bytes, nq)
     print(json.dumps(result), flush=True)
+
+
+def _kernel_sources_digest(kernel):
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2606_06697_amd", "csrc")
+    files = {"validate": ["k_validate.hip"], "triad": ["k_stream.hip"],
+             "gather": ["k_gather.hip"]}[kernel] + ["guard_device.h", "guard_arith.h", "launch.h"]
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, algorithmic):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None when there
+    is none or the kernel's sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_large_table.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("- ") and ":" in line:
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_sources_sha256") != _kernel_sources_digest(kernel):
+        return None
+    try:
+        return int(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def bench_embedding(g, args):
+    """Guarded embedding (1,048,576 x 256 fp32 table, 2^20 Zipf(1.1) indices, 0.01% aimed at a
+    protected range right after the table): forward gather and scatter-add backward, guarded
+    and unguarded (same kernels with the guard compiled out), HIP-event medians."""
+    import numpy as np
+    import torch
+    from synth import uniform_f32, zipf_indices
+
+    R, D, N, PAD = 1 << 20, 256, 1 << 20, 16
+    rb = D * 4
+    dev = torch.device("cuda:0")
+    Wbuf = torch.empty((R + PAD) * D, device=dev)
+    Wbuf[:R * D].copy_(uniform_f32(R * D, 2, device=dev, stream=30))
+    Wbuf[R * D:].fill_(0.0)
+    W = Wbuf[:R * D]
+    idx = zipf_indices(N, R, 1.1, 2, device=dev, bad_frac=1e-4, bad_ranges=((R, R + PAD),))
+    Y = torch.empty(N * D, device=dev)
+    dY = uniform_f32(N * D, 2, device=dev, stream=31)
+    dWbuf = torch.zeros((R + PAD) * D, device=dev)
+    dW = dWbuf[:R * D]
+    t = g.RangeTable(16)
+    t.insert(W.data_ptr(), R * rb, g.KIND_USER)
+    t.insert(W.data_ptr() + R * rb, PAD * rb, g.KIND_PROTECTED)
+    for x in (idx, Y, dY):
+        t.insert_tensor(x, g.KIND_USER)
+    t.insert(dW.data_ptr(), R * rb, g.KIND_USER)
+    ih = idx.cpu().numpy()
+    distinct = int(np.unique(ih[(ih >= 0) & (ih < R)]).size)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    calls = {
+        "forward": lambda: g.agile_guarded_gather(t.handle, Y, W, rb, idx, N),
+        "forward_unguarded": lambda: g.agile_unguarded_gather(Y, Wbuf, rb, idx, N),
+        "backward": lambda: g.agile_guarded_scatter(t.handle, dW, rb, idx, dY, N, 0, 1),
+        "backward_unguarded": lambda: g.agile_unguarded_scatter(dWbuf, rb, idx, dY, N, 0, 1),
+    }
+    ts = {k: [] for k in calls}
+    for rep in range(2 + 5):
+        for k, fn in calls.items():
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            if rep >= 2:
+                ts[k].append(e0.elapsed_time(e1))
+    rc, f = t.fault_log(clear=True)
+    nbad = int(((ih < 0) | (ih >= R)).sum())
+    t.close()
+    med = {k: float(np.median(v)) for k, v in ts.items()}
+    fwd_bytes = N * (8 + 2 * rb)
+    bwd_bytes = N * (8 + rb) + distinct * 2 * rb
+    out = {"workload": "1048576x256 fp32 table, 2^20 Zipf(1.1) idx, 0.01% hostile",
+           "kernel_ms": {k: round(v, 4) for k, v in med.items()},
+           "forward_gbps": round(fwd_bytes / med["forward"] / 1e6, 1),
+           "forward_unguarded_gbps": round(fwd_bytes / med["forward_unguarded"] / 1e6, 1),
+           "backward_gbps": round(bwd_bytes / med["backward"] / 1e6, 1),
+           "backward_unguarded_gbps": round(bwd_bytes / med["backward_unguarded"] / 1e6, 1),
+           "distinct_rows": distinct, "hostile_idx": nbad,
+           "fault_count": int(f["count"])}
+    out["forward_guarded_over_unguarded"] = round(med["forward_unguarded"] / med["forward"], 4)
+    out["backward_guarded_over_unguarded"] = round(med["backward_unguarded"] / med["backward"], 4)
+    return out
+
+
+def bench_batch(g, args):
+    """One persistent launch of 512 requests from 16 clients (4,096-range tables each): pointer
+    arguments (log-uniform 1-4,096 per request) plus one guarded copy per request (log-uniform
+    4 KiB-64 MiB)."""
+    import numpy as np
+    import torch
+    from synth import make_table, make_batch_requests
+
+    ncl, nreq = 16, 512
+    dev = torch.device("cuda:0")
+    tabs = [make_table(4096, 512, 300 + c, first_hi=2**44) for c in range(ncl)]
+    reqspec = make_batch_requests(tabs, nreq, 3)
+    rts = []
+    for tb in tabs:
+        rt = g.RangeTable(4096 + nreq + 8)
+        rt.insert_many(tb.base, tb.size, tb.kind)
+        rts.append(rt)
+    client = reqspec["client"].numpy()
+    cbytes = reqspec["copy_bytes"].numpy()
+    src = [torch.randint(0, 256, (64 << 20,), dtype=torch.uint8, device=dev) for _ in range(ncl)]
+    for c in range(ncl):
+        rts[c].insert_tensor(src[c], g.KIND_USER)
+    dst_total = [int(((cbytes[client == c] + 255) // 256 * 256).sum()) for c in range(ncl)]
+    dst = [torch.empty(max(n, 256), dtype=torch.uint8, device=dev) for n in dst_total]
+    reqs = np.zeros(nreq, dtype=g.REQUEST_DTYPE)
+    off = [0] * ncl
+    rng = np.random.default_rng(5)
+    for r in range(nreq):
+        c = int(client[r])
+        nb = int(cbytes[r])
+        d = dst[c].data_ptr() + off[c]
+        rts[c].insert(d, nb, g.KIND_USER)            # each request's output is its own allocation
+        off[c] += (nb + 255) // 256 * 256
+        reqs[r]["client"] = c
+        reqs[r]["ptr_off"] = int(reqspec["ptr_off"][r])
+        reqs[r]["nptr"] = int(reqspec["ptr_off"][r + 1] - reqspec["ptr_off"][r])
+        reqs[r]["copy_dst"] = d
+        reqs[r]["copy_src"] = src[c].data_ptr() + int(rng.integers(0, ((64 << 20) - nb) // 16 + 1)) * 16
+        reqs[r]["copy_bytes"] = nb
+    P = reqspec["ptrs"].to(dev)
+    nptrs = P.shape[0]
+    pv = torch.empty(nptrs, dtype=torch.uint8, device=dev)
+    po = torch.empty(nptrs, dtype=torch.int32, device=dev)
+    res = torch.empty(nreq * g.RESULT_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    cs = g.agile_clients_create(rts)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = []
+    for rep in range(2 + 5):
+        e0.record()
+        g.agile_batch_run(cs, reqs, P, nptrs, pv, po, res)
+        e1.record()
+        e1.synchronize()
+        if rep >= 2:
+            ts.append(e0.elapsed_time(e1))
+    out_res = g.batch_results(res, nreq)
+    g.agile_clients_destroy(cs)
+    for rt in rts:
+        rt.close()
+    ms = float(np.median(ts))
+    moved = int(cbytes.sum()) * 2
+    return {"workload": "16 clients x 4096 ranges, 512 requests/launch, 1-4096 ptrs + one "
+                        "4 KiB-64 MiB guarded copy per request",
+            "launch_ms": round(ms, 4), "pointers": int(nptrs), "copy_bytes": int(cbytes.sum()),
+            "copy_gbps": round(moved / ms / 1e6, 1),
+            "validations_per_s": round(nptrs / (ms / 1e3), 1),
+            "requests_failing_validation": int((out_res["verdict"] != 0).sum()),
+            "requests_done": int(out_res["done"].sum())}
+
+
+def bench_serving(g, args):
+    """64 clients, Poisson arrivals at 20,000 requests/s, 50% validate / 30% copy / 20% gather,
+    per-client tables of 1,024-8,192 ranges, 32 GiB budget for in-flight outputs."""
+    from paper_2606_06697_amd.serving import Server, ServeConfig
+    from synth import make_serving_trace
+
+    cfg = ServeConfig(duration=args.serve_seconds)
+    srv = Server(cfg)
+    trace = make_serving_trace(cfg.n_clients, cfg.rate, cfg.duration, cfg.seed, mix=cfg.mix,
+                               val_ptrs=cfg.val_ptrs, copy_range=cfg.copy_range,
+                               gather_range=cfg.gather_range)
+    lat, stats, _ = srv.run(trace)
+    srv.close()
+    stats = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in stats.items()}
+    stats["workload"] = (f"64 clients, Poisson 20000 req/s for {cfg.duration:g} s, "
+                         "50/30/20 validate/copy/gather")
+    return stats
 
 
 def cpu_baseline(tb, step_bytes, nq):
