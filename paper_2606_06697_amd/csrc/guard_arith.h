@@ -61,4 +61,39 @@ AGILE_HD inline bool elem_ok(const RowGuard& g, int64_t iv, uint64_t rb, uint64_
     return off >= -(__int128)g.dlo && off + (__int128)W <= (__int128)g.dhi;
 }
 
+// Guard of a row kernel (gather, scatter, scatter-add), fixed for a launch: the readable prefix
+// of the index array, the allowed element prefix of the contiguous operand (out or src), the
+// number of leading rows that pass both (index readable and contiguous row wholly allowed),
+// and the row interval of the row-addressed operand (table or dst).
+struct RowsGuard {
+    uint64_t ki, kc, nfast;
+    RowGuard g;
+};
+
+AGILE_HD inline RowsGuard rows_guard(Bind bi, Bind bc, Bind br, uint64_t idx, uint64_t cptr,
+                                     uint64_t rptr, uint64_t n, uint64_t rb, uint32_t W) {
+    RowsGuard r;
+    const uint64_t D = rb / W;
+    r.ki = clip_prefix(bi, idx, n, 8);
+    r.kc = clip_prefix(bc, cptr, n * D, W);
+    const uint64_t crows = r.kc / D;
+    r.nfast = r.ki < crows ? r.ki : crows;
+    r.g = row_guard(br, rptr, rb);
+    return r;
+}
+
+// The same shape with every access allowed (the unguarded twins).
+AGILE_HD inline RowsGuard rows_open(uint64_t n, uint64_t rb, uint32_t W) {
+    RowsGuard r;
+    r.ki = n;
+    r.kc = n * (rb / W);
+    r.nfast = n;
+    r.g.rlo = INT64_MIN;
+    r.g.rhi = INT64_MAX;
+    r.g.dlo = 0;
+    r.g.dhi = 0;
+    r.g.bound = true;
+    return r;
+}
+
 }  // namespace agile

@@ -270,6 +270,8 @@ __device__ inline void fold_faults(FaultAcc acc, DevLog* log, const Payload& pay
     }
 }
 
+// Out of line: runs once per launch (last workgroup), so it should not add to the registers of
+// the kernels' main loops.
 __device__ inline void record_at(const DevTable& t, DevLog* log, unsigned long long seq,
                                  unsigned long long elem, uint32_t operand, __int128 A, uint32_t w,
                                  uint32_t op) {

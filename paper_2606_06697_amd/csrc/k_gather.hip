@@ -1,11 +1,11 @@
 // Guarded gather and scatter(-add) over rows (kernel memory guard of AgileOS Section V-E).
 //
 // out[i,:] = T[idx[i],:]  /  dst[idx[i],:] (+)= src[i,:], rows of `rb` bytes, elements of W bytes.
-// Every wave binds the three pointer arguments once (wave-cooperative table search, bounds in
-// scalar registers). The index and the contiguous operand have prefix-shaped allowed sets; for
-// the row-addressed operand the binding becomes an index interval [rlo, rhi] of rows that lie
-// wholly inside the allocation, so the per-row guard is two signed compares of the loaded
-// index against scalars. Rows outside it (hostile indices, or a table pointer that is not
+// The three pointer arguments are bound once per call (host lookup in the table the launch is
+// ordered after) and reach the kernel as scalars. The index and the contiguous operand have
+// prefix-shaped allowed sets; for the row-addressed operand the binding becomes an index
+// interval [rlo, rhi] of rows that lie wholly inside the allocation, so the per-row guard is
+// two signed compares of the loaded index against scalars. Rows outside it (hostile indices, or a table pointer that is not
 // row-aligned with its allocation's ends) take an exact 128-bit per-element path. Denials are
 // counted per lane, reduced per wave, and folded into the handle's log: the smallest
 // (element, operand) key wins, and the last workgroup to finish writes that denial's record.
@@ -15,7 +15,6 @@
 namespace agile {
 
 constexpr int GBLOCK = 256;
-constexpr int GROWS = 4;  // rows in flight per lane group
 
 template <int B>
 struct Word;
@@ -33,10 +32,45 @@ struct Word<16> {
     using T = u32x4;
 };
 
-template <bool GUARD, int CW, int W>
+// Lane layout shared by both kernels: a row is covered by G = 2^glog2 lanes (one CW-byte chunk
+// each per pass), a wave covers 64/G rows, and each lane keeps R rows in flight. WIDE kernels
+// give a whole wave to each row (G = 64), so a row's index is wave-uniform and its guard test
+// runs on scalar registers.
+struct RowLanes {
+    uint32_t G, lir, riw;
+    uint64_t rpw, wave, nwaves;
+    __device__ explicit RowLanes(uint32_t glog2) {
+        const uint32_t lane = threadIdx.x & 63u;
+        G = 1u << glog2;
+        lir = lane & (G - 1);
+        riw = lane >> glog2;
+        rpw = 64u >> glog2;
+        wave = ((uint64_t)blockIdx.x * GBLOCK + threadIdx.x) >> 6;
+        nwaves = ((uint64_t)gridDim.x * GBLOCK) >> 6;
+    }
+};
+
+// Per pass, every lane first issues the loads of all its rows that pass the fast test, then the
+// matching stores, and only then runs the exact per-element path for the rest, so the guard
+// adds no wait between the R independent loads. The fast test of row i is i < nfast (its index
+// is readable and its contiguous-operand row is wholly allowed: both are prefixes) and
+// rlo <= idx[i] <= rhi (its row-addressed row is wholly inside the binding).
+template <bool GUARD, bool WIDE, int R>
+__device__ __forceinline__ void load_rows(const RowLanes& L, uint64_t r0, uint64_t nfast,
+                                          const int64_t* idx, int64_t (&iv)[R]) {
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+        const uint64_t i = r0 + u * L.rpw + L.riw;
+        int64_t x = i < nfast ? idx[i] : 0;
+        if (WIDE) x = (int64_t)uniform_u64((uint64_t)x);
+        iv[u] = x;
+    }
+}
+
+template <bool GUARD, int CW, int W, int R, bool WIDE>
 __global__ __launch_bounds__(GBLOCK) void k_gather(DevTable t, DevLog* log, uint8_t* out,
                                                     const uint8_t* T, uint64_t rb,
-                                                    const int64_t* idx, uint64_t n,
+                                                    const int64_t* idx, uint64_t n, RowsGuard rg,
                                                     unsigned long long seq, int logon,
                                                     uint32_t glog2) {
     using V = typename Word<CW>::T;
@@ -44,60 +78,54 @@ __global__ __launch_bounds__(GBLOCK) void k_gather(DevTable t, DevLog* log, uint
     constexpr uint32_t EPC = CW / W;  // elements per chunk
     const uint64_t D = rb / W;
     const uint64_t nch = rb / CW;
-    uint64_t Ki = n, Ko = n * D;
-    RowGuard g{INT64_MIN, INT64_MAX, 0, 0, true};
-    if (GUARD) {
-        const Bind bi = bind_wave(t, (uint64_t)idx);
-        const Bind bt = bind_wave(t, (uint64_t)T);
-        const Bind bo = bind_wave(t, (uint64_t)out);
-        Ki = clip_prefix(bi, (uint64_t)idx, n, 8);
-        Ko = clip_prefix(bo, (uint64_t)out, n * D, W);
-        g = row_guard(bt, (uint64_t)T, rb);
-    }
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t G = 1u << glog2;
-    const uint32_t lir = lane & (G - 1);
-    const uint32_t riw = lane >> glog2;
-    const uint64_t rpw = 64u >> glog2;  // rows per wave
-    const uint64_t wave = ((uint64_t)blockIdx.x * GBLOCK + threadIdx.x) >> 6;
-    const uint64_t nwaves = ((uint64_t)gridDim.x * GBLOCK) >> 6;
+    const uint64_t Ki = rg.ki, Ko = rg.kc, nfast = rg.nfast;
+    const RowGuard g = rg.g;
+    const RowLanes L(WIDE ? 6u : glog2);
     FaultAcc acc;
-    for (uint64_t r0 = wave * rpw * GROWS; r0 < n; r0 += nwaves * rpw * GROWS) {
-        int64_t iv[GROWS];
-        bool live[GROWS];
+    for (uint64_t r0 = L.wave * L.rpw * R; r0 < n; r0 += L.nwaves * L.rpw * R) {
+        int64_t iv[R];
+        load_rows<GUARD, WIDE, R>(L, r0, nfast, idx, iv);
+        for (uint64_t c0 = 0; c0 < nch; c0 += L.G) {
+            const uint64_t ch = c0 + L.lir;
+            V v[R];
+            uint32_t slow = 0;  // rows of this lane whose chunk takes the exact path
 #pragma unroll
-        for (int u = 0; u < GROWS; ++u) {
-            const uint64_t i = r0 + u * rpw + riw;
-            live[u] = i < n;
-            const bool iok = !GUARD || i < Ki;
-            iv[u] = (live[u] && iok) ? idx[i] : 0;
-            if (GUARD && live[u] && !iok && lir == 0) acc.note((i * D) << 2);
-        }
+            for (int u = 0; u < R; ++u) {
+                const uint64_t i = r0 + u * L.rpw + L.riw;
+                const bool on = i < n && ch < nch;
+                const bool fast = on && (!GUARD || (i < nfast && g.rlo <= iv[u] && iv[u] <= g.rhi));
+                if (fast) v[u] = *reinterpret_cast<const V*>(T + (uint64_t)iv[u] * rb + ch * CW);
+                if (on && !fast) slow |= 1u << u;
+            }
 #pragma unroll
-        for (int u = 0; u < GROWS; ++u) {
-            if (!live[u]) continue;
-            const uint64_t i = r0 + u * rpw + riw;
-            const bool full = !GUARD || (g.rlo <= iv[u] && iv[u] <= g.rhi);
-            const uint8_t* trow = T + (uint64_t)iv[u] * rb;
-            uint8_t* orow = out + i * rb;
-            for (uint64_t ch = lir; ch < nch; ch += G) {
-                const uint64_t e0 = i * D + ch * EPC;
-                if (full && (!GUARD || e0 + EPC <= Ko)) {
-                    *reinterpret_cast<V*>(orow + ch * CW) = *reinterpret_cast<const V*>(trow + ch * CW);
-                } else {
-#pragma unroll
-                    for (uint32_t k = 0; k < EPC; ++k) {
-                        const uint64_t col = ch * EPC + k;
-                        const uint64_t e = e0 + k;
-                        E val = 0;
-                        if (full || elem_ok(g, iv[u], rb, col, W)) {
-                            val = *reinterpret_cast<const E*>(trow + col * W);
-                        } else {
-                            acc.note((e << 2) | 1u);
-                        }
-                        if (e < Ko) *reinterpret_cast<E*>(orow + col * W) = val;
-                        else acc.note((e << 2) | 2u);
+            for (int u = 0; u < R; ++u) {
+                const uint64_t i = r0 + u * L.rpw + L.riw;
+                if (i < n && ch < nch && !((slow >> u) & 1u))
+                    __builtin_nontemporal_store(v[u], reinterpret_cast<V*>(out + i * rb + ch * CW));
+            }
+            if (!GUARD || slow == 0) continue;
+#pragma unroll 1
+            for (int u = 0; u < R; ++u) {
+                if (!((slow >> u) & 1u)) continue;
+                const uint64_t i = r0 + u * L.rpw + L.riw;
+                const bool iok = i < Ki;
+                if (!iok && ch == 0) acc.note((i * D) << 2);  // one 8-byte index load per row
+                const int64_t x = iok ? idx[i] : 0;
+                const bool full = g.rlo <= x && x <= g.rhi;
+                const uint8_t* trow = T + (uint64_t)x * rb;
+                uint8_t* orow = out + i * rb;
+#pragma unroll 1
+                for (uint32_t k = 0; k < EPC; ++k) {
+                    const uint64_t col = ch * EPC + k;
+                    const uint64_t e = i * D + col;
+                    E val = 0;
+                    if (full || elem_ok(g, x, rb, col, W)) {
+                        val = *reinterpret_cast<const E*>(trow + col * W);
+                    } else {
+                        acc.note((e << 2) | 1u);
                     }
+                    if (e < Ko) *reinterpret_cast<E*>(orow + col * W) = val;
+                    else acc.note((e << 2) | 2u);
                 }
             }
         }
@@ -123,77 +151,65 @@ __global__ __launch_bounds__(GBLOCK) void k_gather(DevTable t, DevLog* log, uint
     }
 }
 
-template <bool GUARD, int CW, int W, bool ACC>
+// Plain scatter (no accumulation): with duplicate indices one of the writers wins.
+template <bool GUARD, int CW, int W, int R, bool WIDE>
 __global__ __launch_bounds__(GBLOCK) void k_scatter(DevTable t, DevLog* log, uint8_t* dst,
                                                      uint64_t rb, const int64_t* idx,
-                                                     const uint8_t* src, uint64_t n,
+                                                     const uint8_t* src, uint64_t n, RowsGuard rg,
                                                      unsigned long long seq, int logon,
                                                      uint32_t glog2) {
     using V = typename Word<CW>::T;
     using E = typename Word<W>::T;
-    using F = typename std::conditional<W == 4, float, double>::type;
     constexpr uint32_t EPC = CW / W;
     const uint64_t D = rb / W;
     const uint64_t nch = rb / CW;
-    uint64_t Ki = n, Ks = n * D;
-    RowGuard g{INT64_MIN, INT64_MAX, 0, 0, true};
-    if (GUARD) {
-        const Bind bi = bind_wave(t, (uint64_t)idx);
-        const Bind bs = bind_wave(t, (uint64_t)src);
-        const Bind bd = bind_wave(t, (uint64_t)dst);
-        Ki = clip_prefix(bi, (uint64_t)idx, n, 8);
-        Ks = clip_prefix(bs, (uint64_t)src, n * D, W);
-        g = row_guard(bd, (uint64_t)dst, rb);
-    }
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t G = 1u << glog2;
-    const uint32_t lir = lane & (G - 1);
-    const uint32_t riw = lane >> glog2;
-    const uint64_t rpw = 64u >> glog2;
-    const uint64_t wave = ((uint64_t)blockIdx.x * GBLOCK + threadIdx.x) >> 6;
-    const uint64_t nwaves = ((uint64_t)gridDim.x * GBLOCK) >> 6;
+    const uint64_t Ki = rg.ki, Ks = rg.kc, nfast = rg.nfast;
+    const RowGuard g = rg.g;
+    const RowLanes L(WIDE ? 6u : glog2);
     FaultAcc acc;
-    for (uint64_t r0 = wave * rpw * GROWS; r0 < n; r0 += nwaves * rpw * GROWS) {
-        int64_t iv[GROWS];
-        bool live[GROWS];
+    for (uint64_t r0 = L.wave * L.rpw * R; r0 < n; r0 += L.nwaves * L.rpw * R) {
+        int64_t iv[R];
+        load_rows<GUARD, WIDE, R>(L, r0, nfast, idx, iv);
+        for (uint64_t c0 = 0; c0 < nch; c0 += L.G) {
+            const uint64_t ch = c0 + L.lir;
+            V v[R];
+            uint32_t slow = 0;
 #pragma unroll
-        for (int u = 0; u < GROWS; ++u) {
-            const uint64_t i = r0 + u * rpw + riw;
-            live[u] = i < n;
-            const bool iok = !GUARD || i < Ki;
-            iv[u] = (live[u] && iok) ? idx[i] : 0;
-            if (GUARD && live[u] && !iok && lir == 0) acc.note((i * D) << 2);
-        }
+            for (int u = 0; u < R; ++u) {
+                const uint64_t i = r0 + u * L.rpw + L.riw;
+                const bool on = i < n && ch < nch;
+                const bool fast = on && (!GUARD || (i < nfast && g.rlo <= iv[u] && iv[u] <= g.rhi));
+                if (fast) v[u] = *reinterpret_cast<const V*>(src + i * rb + ch * CW);
+                if (on && !fast) slow |= 1u << u;
+            }
 #pragma unroll
-        for (int u = 0; u < GROWS; ++u) {
-            if (!live[u]) continue;
-            const uint64_t i = r0 + u * rpw + riw;
-            const bool full = !GUARD || (g.rlo <= iv[u] && iv[u] <= g.rhi);
-            uint8_t* drow = dst + (uint64_t)iv[u] * rb;
-            const uint8_t* srow = src + i * rb;
-            for (uint64_t ch = lir; ch < nch; ch += G) {
-                const uint64_t e0 = i * D + ch * EPC;
-                if (!ACC && full && (!GUARD || e0 + EPC <= Ks)) {
-                    *reinterpret_cast<V*>(drow + ch * CW) = *reinterpret_cast<const V*>(srow + ch * CW);
-                } else {
-#pragma unroll
-                    for (uint32_t k = 0; k < EPC; ++k) {
-                        const uint64_t col = ch * EPC + k;
-                        const uint64_t e = e0 + k;
-                        E val = 0;
-                        if (!GUARD || e < Ks) val = *reinterpret_cast<const E*>(srow + col * W);
-                        else acc.note((e << 2) | 1u);
-                        if (full || elem_ok(g, iv[u], rb, col, W)) {
-                            if (ACC) {
-                                F fv;
-                                __builtin_memcpy(&fv, &val, W);
-                                unsafeAtomicAdd(reinterpret_cast<F*>(drow + col * W), fv);
-                            } else {
-                                *reinterpret_cast<E*>(drow + col * W) = val;
-                            }
-                        } else {
-                            acc.note((e << 2) | 2u);
-                        }
+            for (int u = 0; u < R; ++u) {
+                const uint64_t i = r0 + u * L.rpw + L.riw;
+                if (i < n && ch < nch && !((slow >> u) & 1u))
+                    *reinterpret_cast<V*>(dst + (uint64_t)iv[u] * rb + ch * CW) = v[u];
+            }
+            if (!GUARD || slow == 0) continue;
+#pragma unroll 1
+            for (int u = 0; u < R; ++u) {
+                if (!((slow >> u) & 1u)) continue;
+                const uint64_t i = r0 + u * L.rpw + L.riw;
+                const bool iok = i < Ki;
+                if (!iok && ch == 0) acc.note((i * D) << 2);
+                const int64_t x = iok ? idx[i] : 0;
+                const bool full = g.rlo <= x && x <= g.rhi;
+                uint8_t* drow = dst + (uint64_t)x * rb;
+                const uint8_t* srow = src + i * rb;
+#pragma unroll 1
+                for (uint32_t k = 0; k < EPC; ++k) {
+                    const uint64_t col = ch * EPC + k;
+                    const uint64_t e = i * D + col;
+                    E val = 0;
+                    if (e < Ks) val = *reinterpret_cast<const E*>(srow + col * W);
+                    else acc.note((e << 2) | 1u);
+                    if (full || elem_ok(g, x, rb, col, W)) {
+                        *reinterpret_cast<E*>(drow + col * W) = val;
+                    } else {
+                        acc.note((e << 2) | 2u);
                     }
                 }
             }
@@ -215,7 +231,7 @@ __global__ __launch_bounds__(GBLOCK) void k_scatter(DevTable t, DevLog* log, uin
                 const int64_t v = i < Ki ? idx[i] : 0;
                 A = (__int128)(uint64_t)dst + (__int128)v * (__int128)rb + (__int128)(col * W);
             }
-            record_at(t, log, seq, elem, operand, A, w, ACC ? 5 : 4);
+            record_at(t, log, seq, elem, operand, A, w, 4 /*OP_SCATTER*/);
         });
     }
 }
@@ -249,73 +265,111 @@ static uint32_t lanes_log2(uint64_t nch) {
     return l;
 }
 
-static uint32_t rows_grid(uint64_t n, uint32_t glog2, const DevInfo& d) {
-    const uint64_t rows_per_block = (uint64_t)(GBLOCK / 64) * (64u >> glog2) * GROWS;
+// Rows in flight per lane: more for narrow rows, where each load is a lone random access, and
+// for rows that take a whole wave, where the row's index and guard live in scalar registers.
+constexpr int R_NARROW = 8, R_WIDE = 4, R_ROWWAVE = 8;
+
+static uint32_t rows_grid(uint64_t n, uint32_t glog2, int R, const DevInfo& d) {
+    const uint64_t rows_per_block = (uint64_t)(GBLOCK / 64) * (64u >> glog2) * R;
     uint64_t want = (n + rows_per_block - 1) / rows_per_block;
-    const uint64_t cap = (uint64_t)d.num_cu * 8;
+    const uint64_t cap = (uint64_t)d.num_cu * 4;  // measured best of 1, 2, 4, 8, 16 per CU
     if (want < 1) want = 1;
     return (uint32_t)(want < cap ? want : cap);
 }
 
-template <bool G, int W>
-static void gather_w(const DevTable& t, DevLog* log, void* out, const void* tab, uint64_t rb,
-                     const int64_t* idx, uint64_t n, unsigned long long seq, int logon,
-                     const DevInfo& d, hipStream_t s) {
-    const bool v16 = rb % 16 == 0 && (((uint64_t)out | (uint64_t)tab) & 15) == 0;
-    const uint64_t nch = v16 ? rb / 16 : rb / W;
-    const uint32_t gl = lanes_log2(nch);
-    const dim3 grid(rows_grid(n, gl, d)), block(GBLOCK);
-    if (v16)
-        hipLaunchKernelGGL((k_gather<G, 16, W>), grid, block, 0, s, t, log, (uint8_t*)out,
-                           (const uint8_t*)tab, rb, idx, n, seq, logon, gl);
+template <bool G, int CW, int W>
+static void gather_cw(const DevTable& t, DevLog* log, void* out, const void* tab, uint64_t rb,
+                      const int64_t* idx, uint64_t n, const RowsGuard& rg, unsigned long long seq,
+                      int logon, const DevInfo& d, hipStream_t s) {
+    const uint32_t gl = lanes_log2(rb / CW);
+    const dim3 block(GBLOCK);
+    if (gl == 6)
+        hipLaunchKernelGGL((k_gather<G, CW, W, R_ROWWAVE, true>), dim3(rows_grid(n, gl, R_ROWWAVE, d)),
+                           block, 0, s, t, log, (uint8_t*)out, (const uint8_t*)tab, rb, idx, n, rg, seq,
+                           logon, gl);
+    else if (rb <= 16)
+        hipLaunchKernelGGL((k_gather<G, CW, W, R_NARROW, false>), dim3(rows_grid(n, gl, R_NARROW, d)),
+                           block, 0, s, t, log, (uint8_t*)out, (const uint8_t*)tab, rb, idx, n, rg, seq,
+                           logon, gl);
     else
-        hipLaunchKernelGGL((k_gather<G, W, W>), grid, block, 0, s, t, log, (uint8_t*)out,
-                           (const uint8_t*)tab, rb, idx, n, seq, logon, gl);
+        hipLaunchKernelGGL((k_gather<G, CW, W, R_WIDE, false>), dim3(rows_grid(n, gl, R_WIDE, d)),
+                           block, 0, s, t, log, (uint8_t*)out, (const uint8_t*)tab, rb, idx, n, rg, seq,
+                           logon, gl);
 }
 
-hipError_t launch_gather(bool guard, const DevTable& t, DevLog* log, void* out, const void* tab,
-                         uint64_t rb, const int64_t* idx, uint64_t n, uint32_t w,
+template <bool G, int W>
+static void gather_w(const DevTable& t, DevLog* log, void* out, const void* tab, uint64_t rb,
+                     const int64_t* idx, uint64_t n, const RowsGuard& rg, unsigned long long seq,
+                     int logon, const DevInfo& d, hipStream_t s) {
+    if (rb % 16 == 0 && (((uint64_t)out | (uint64_t)tab) & 15) == 0)
+        gather_cw<G, 16, W>(t, log, out, tab, rb, idx, n, rg, seq, logon, d, s);
+    else
+        gather_cw<G, W, W>(t, log, out, tab, rb, idx, n, rg, seq, logon, d, s);
+}
+
+hipError_t launch_gather(bool guard, const DevTable& t, DevLog* log, const Bind* binds, void* out,
+                         const void* tab, uint64_t rb, const int64_t* idx, uint64_t n, uint32_t w,
                          unsigned long long seq, int logon, const DevInfo& d, hipStream_t s) {
     if (n == 0) return hipSuccess;
     if (guard) {
-        if (w == 4) gather_w<true, 4>(t, log, out, tab, rb, idx, n, seq, logon, d, s);
-        else gather_w<true, 8>(t, log, out, tab, rb, idx, n, seq, logon, d, s);
+        const RowsGuard rg = rows_guard(binds[0], binds[2], binds[1], (uint64_t)idx, (uint64_t)out,
+                                        (uint64_t)tab, n, rb, w);
+        if (w == 4) gather_w<true, 4>(t, log, out, tab, rb, idx, n, rg, seq, logon, d, s);
+        else gather_w<true, 8>(t, log, out, tab, rb, idx, n, rg, seq, logon, d, s);
     } else {
-        if (w == 4) gather_w<false, 4>(t, log, out, tab, rb, idx, n, seq, logon, d, s);
-        else gather_w<false, 8>(t, log, out, tab, rb, idx, n, seq, logon, d, s);
+        const RowsGuard rg = rows_open(n, rb, w);
+        if (w == 4) gather_w<false, 4>(t, log, out, tab, rb, idx, n, rg, seq, logon, d, s);
+        else gather_w<false, 8>(t, log, out, tab, rb, idx, n, rg, seq, logon, d, s);
     }
     return hipGetLastError();
 }
 
-template <bool G, int W, bool ACC>
-static void scatter_w(const DevTable& t, DevLog* log, void* dst, uint64_t rb, const int64_t* idx,
-                      const void* src, uint64_t n, unsigned long long seq, int logon,
-                      const DevInfo& d, hipStream_t s) {
-    const bool v16 = !ACC && rb % 16 == 0 && (((uint64_t)dst | (uint64_t)src) & 15) == 0;
-    const uint64_t nch = v16 ? rb / 16 : rb / W;
-    const uint32_t gl = lanes_log2(nch);
-    const dim3 grid(rows_grid(n, gl, d)), block(GBLOCK);
-    if (v16)
-        hipLaunchKernelGGL((k_scatter<G, 16, W, ACC>), grid, block, 0, s, t, log, (uint8_t*)dst, rb,
-                           idx, (const uint8_t*)src, n, seq, logon, gl);
+template <bool G, int CW, int W>
+static void scatter_cw(const DevTable& t, DevLog* log, void* dst, uint64_t rb, const int64_t* idx,
+                       const void* src, uint64_t n, const RowsGuard& rg, unsigned long long seq,
+                       int logon, const DevInfo& d, hipStream_t s) {
+    const uint32_t gl = lanes_log2(rb / CW);
+    const dim3 block(GBLOCK);
+    if (gl == 6)
+        hipLaunchKernelGGL((k_scatter<G, CW, W, R_ROWWAVE, true>), dim3(rows_grid(n, gl, R_ROWWAVE, d)),
+                           block, 0, s, t, log, (uint8_t*)dst, rb, idx, (const uint8_t*)src, n, rg, seq,
+                           logon, gl);
+    else if (rb <= 16)
+        hipLaunchKernelGGL((k_scatter<G, CW, W, R_NARROW, false>), dim3(rows_grid(n, gl, R_NARROW, d)),
+                           block, 0, s, t, log, (uint8_t*)dst, rb, idx, (const uint8_t*)src, n, rg, seq,
+                           logon, gl);
     else
-        hipLaunchKernelGGL((k_scatter<G, W, W, ACC>), grid, block, 0, s, t, log, (uint8_t*)dst, rb,
-                           idx, (const uint8_t*)src, n, seq, logon, gl);
+        hipLaunchKernelGGL((k_scatter<G, CW, W, R_WIDE, false>), dim3(rows_grid(n, gl, R_WIDE, d)),
+                           block, 0, s, t, log, (uint8_t*)dst, rb, idx, (const uint8_t*)src, n, rg, seq,
+                           logon, gl);
 }
 
-hipError_t launch_scatter(bool guard, const DevTable& t, DevLog* log, void* dst, uint64_t rb,
-                          const int64_t* idx, const void* src, uint64_t n, uint32_t w,
+template <bool G, int W>
+static void scatter_w(const DevTable& t, DevLog* log, void* dst, uint64_t rb, const int64_t* idx,
+                      const void* src, uint64_t n, const RowsGuard& rg, unsigned long long seq,
+                      int logon, const DevInfo& d, hipStream_t s) {
+    if (rb % 16 == 0 && (((uint64_t)dst | (uint64_t)src) & 15) == 0)
+        scatter_cw<G, 16, W>(t, log, dst, rb, idx, src, n, rg, seq, logon, d, s);
+    else
+        scatter_cw<G, W, W>(t, log, dst, rb, idx, src, n, rg, seq, logon, d, s);
+}
+
+hipError_t launch_scatter(bool guard, const DevTable& t, DevLog* log, const Bind* binds, void* dst,
+                          uint64_t rb, const int64_t* idx, const void* src, uint64_t n, uint32_t w,
                           int accumulate, unsigned long long seq, int logon, const DevInfo& d,
                           hipStream_t s) {
     if (n == 0) return hipSuccess;
     if (accumulate)
-        return launch_scatter_add(guard, t, log, dst, rb, idx, src, n, w, seq, logon, d, s);
+        return launch_scatter_add(guard, t, log, binds, dst, rb, idx, src, n, w, seq, logon, d, s);
     if (guard) {
-        if (w == 4) scatter_w<true, 4, false>(t, log, dst, rb, idx, src, n, seq, logon, d, s);
-        else scatter_w<true, 8, false>(t, log, dst, rb, idx, src, n, seq, logon, d, s);
+        const RowsGuard rg = rows_guard(binds[0], binds[1], binds[2], (uint64_t)idx, (uint64_t)src,
+                                        (uint64_t)dst, n, rb, w);
+        if (w == 4) scatter_w<true, 4>(t, log, dst, rb, idx, src, n, rg, seq, logon, d, s);
+        else scatter_w<true, 8>(t, log, dst, rb, idx, src, n, rg, seq, logon, d, s);
     } else {
-        if (w == 4) scatter_w<false, 4, false>(t, log, dst, rb, idx, src, n, seq, logon, d, s);
-        else scatter_w<false, 8, false>(t, log, dst, rb, idx, src, n, seq, logon, d, s);
+        const RowsGuard rg = rows_open(n, rb, w);
+        if (w == 4) scatter_w<false, 4>(t, log, dst, rb, idx, src, n, rg, seq, logon, d, s);
+        else scatter_w<false, 8>(t, log, dst, rb, idx, src, n, rg, seq, logon, d, s);
     }
     return hipGetLastError();
 }

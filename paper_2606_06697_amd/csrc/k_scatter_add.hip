@@ -60,7 +60,8 @@ template <bool GUARD, int W, int EPL>
 __global__ __launch_bounds__(SABLOCK) void k_scatter_add(DevTable t, DevLog* log, uint8_t* dst,
                                                          uint64_t rb, const int64_t* idx,
                                                          const uint8_t* src, uint64_t n,
-                                                         unsigned long long seq, int logon) {
+                                                         RowsGuard rg, unsigned long long seq,
+                                                         int logon) {
     using F = typename FloatOf<W>::F;
     __shared__ uint64_t skey[SACHUNK];
     __shared__ uint16_t spos[SACHUNK];
@@ -69,16 +70,8 @@ __global__ __launch_bounds__(SABLOCK) void k_scatter_add(DevTable t, DevLog* log
     __shared__ uint32_t snp;
 
     const uint64_t D = rb / W;
-    uint64_t Ki = n, Ks = n * D;
-    RowGuard g{INT64_MIN, INT64_MAX, 0, 0, true};
-    if (GUARD) {
-        const Bind bi = bind_wave(t, (uint64_t)idx);
-        const Bind bs = bind_wave(t, (uint64_t)src);
-        const Bind bd = bind_wave(t, (uint64_t)dst);
-        Ki = clip_prefix(bi, (uint64_t)idx, n, 8);
-        Ks = clip_prefix(bs, (uint64_t)src, n * D, W);
-        g = row_guard(bd, (uint64_t)dst, rb);
-    }
+    const uint64_t Ki = rg.ki, Ks = rg.kc;
+    const RowGuard g = rg.g;
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
     constexpr uint32_t NWV = SABLOCK / 64;
     FaultAcc acc;
@@ -220,7 +213,7 @@ __global__ __launch_bounds__(SABLOCK) void k_scatter_add(DevTable t, DevLog* log
 
 template <bool G, int W>
 static void scatter_add_w(const DevTable& t, DevLog* log, void* dst, uint64_t rb,
-                          const int64_t* idx, const void* src, uint64_t n,
+                          const int64_t* idx, const void* src, uint64_t n, const RowsGuard& rg,
                           unsigned long long seq, int logon, const DevInfo& d, hipStream_t s) {
     uint64_t grid = (n + SACHUNK - 1) / SACHUNK;
     const uint64_t cap = (uint64_t)d.num_cu * 4;
@@ -228,22 +221,26 @@ static void scatter_add_w(const DevTable& t, DevLog* log, void* dst, uint64_t rb
     const bool v4 = W == 4 && (rb / W) % 4 == 0 && ((uint64_t)src & 15) == 0;
     if (v4)
         hipLaunchKernelGGL((k_scatter_add<G, W, 4>), dim3((uint32_t)grid), dim3(SABLOCK), 0, s, t, log,
-                           (uint8_t*)dst, rb, idx, (const uint8_t*)src, n, seq, logon);
+                           (uint8_t*)dst, rb, idx, (const uint8_t*)src, n, rg, seq, logon);
     else
         hipLaunchKernelGGL((k_scatter_add<G, W, 1>), dim3((uint32_t)grid), dim3(SABLOCK), 0, s, t, log,
-                           (uint8_t*)dst, rb, idx, (const uint8_t*)src, n, seq, logon);
+                           (uint8_t*)dst, rb, idx, (const uint8_t*)src, n, rg, seq, logon);
 }
 
-hipError_t launch_scatter_add(bool guard, const DevTable& t, DevLog* log, void* dst, uint64_t rb,
-                              const int64_t* idx, const void* src, uint64_t n, uint32_t w,
-                              unsigned long long seq, int logon, const DevInfo& d, hipStream_t s) {
+hipError_t launch_scatter_add(bool guard, const DevTable& t, DevLog* log, const Bind* binds,
+                              void* dst, uint64_t rb, const int64_t* idx, const void* src,
+                              uint64_t n, uint32_t w, unsigned long long seq, int logon,
+                              const DevInfo& d, hipStream_t s) {
     if (n == 0) return hipSuccess;
     if (guard) {
-        if (w == 4) scatter_add_w<true, 4>(t, log, dst, rb, idx, src, n, seq, logon, d, s);
-        else scatter_add_w<true, 8>(t, log, dst, rb, idx, src, n, seq, logon, d, s);
+        const RowsGuard rg = rows_guard(binds[0], binds[1], binds[2], (uint64_t)idx, (uint64_t)src,
+                                        (uint64_t)dst, n, rb, w);
+        if (w == 4) scatter_add_w<true, 4>(t, log, dst, rb, idx, src, n, rg, seq, logon, d, s);
+        else scatter_add_w<true, 8>(t, log, dst, rb, idx, src, n, rg, seq, logon, d, s);
     } else {
-        if (w == 4) scatter_add_w<false, 4>(t, log, dst, rb, idx, src, n, seq, logon, d, s);
-        else scatter_add_w<false, 8>(t, log, dst, rb, idx, src, n, seq, logon, d, s);
+        const RowsGuard rg = rows_open(n, rb, w);
+        if (w == 4) scatter_add_w<false, 4>(t, log, dst, rb, idx, src, n, rg, seq, logon, d, s);
+        else scatter_add_w<false, 8>(t, log, dst, rb, idx, src, n, rg, seq, logon, d, s);
     }
     return hipGetLastError();
 }

@@ -19,26 +19,32 @@ constexpr uint32_t MAX_RADIX = (1u << 14) + 1;
 hipError_t launch_validate(const DevTable& t, const DevInfo& d, const void* q, uint64_t n,
                            uint8_t* verdict, int32_t* owner, hipStream_t s);
 
-hipError_t launch_copy(bool guard, const DevTable& t, DevLog* log, void* dst, const void* src,
-                       uint64_t n, unsigned long long seq, int logon, const DevInfo& d,
-                       hipStream_t s);
+// Guarded launches take the bindings of their pointer arguments, looked up on the host from the
+// table the launch is ordered after (`binds` in the operand order of the operation: copy src,
+// dst; triad b, c, a; gather idx, table, out; scatter idx, src, dst). With guard == false
+// `binds` is ignored and may be null.
+hipError_t launch_copy(bool guard, const DevTable& t, DevLog* log, const Bind* binds, void* dst,
+                       const void* src, uint64_t n, unsigned long long seq, int logon,
+                       const DevInfo& d, hipStream_t s);
 
-hipError_t launch_triad(bool guard, const DevTable& t, DevLog* log, float* a, const float* b,
-                        const float* c, float sc, uint64_t n, unsigned long long seq, int logon,
-                        const DevInfo& d, hipStream_t s);
+hipError_t launch_triad(bool guard, const DevTable& t, DevLog* log, const Bind* binds, float* a,
+                        const float* b, const float* c, float sc, uint64_t n,
+                        unsigned long long seq, int logon, const DevInfo& d, hipStream_t s);
 
-hipError_t launch_gather(bool guard, const DevTable& t, DevLog* log, void* out, const void* tab,
-                         uint64_t row_bytes, const int64_t* idx, uint64_t n, uint32_t w,
-                         unsigned long long seq, int logon, const DevInfo& d, hipStream_t s);
+hipError_t launch_gather(bool guard, const DevTable& t, DevLog* log, const Bind* binds, void* out,
+                         const void* tab, uint64_t row_bytes, const int64_t* idx, uint64_t n,
+                         uint32_t w, unsigned long long seq, int logon, const DevInfo& d,
+                         hipStream_t s);
 
-hipError_t launch_scatter(bool guard, const DevTable& t, DevLog* log, void* dst,
+hipError_t launch_scatter(bool guard, const DevTable& t, DevLog* log, const Bind* binds, void* dst,
                           uint64_t row_bytes, const int64_t* idx, const void* src, uint64_t n,
                           uint32_t w, int accumulate, unsigned long long seq, int logon,
                           const DevInfo& d, hipStream_t s);
 
-hipError_t launch_scatter_add(bool guard, const DevTable& t, DevLog* log, void* dst, uint64_t rb,
-                              const int64_t* idx, const void* src, uint64_t n, uint32_t w,
-                              unsigned long long seq, int logon, const DevInfo& d, hipStream_t s);
+hipError_t launch_scatter_add(bool guard, const DevTable& t, DevLog* log, const Bind* binds,
+                              void* dst, uint64_t rb, const int64_t* idx, const void* src,
+                              uint64_t n, uint32_t w, unsigned long long seq, int logon,
+                              const DevInfo& d, hipStream_t s);
 
 hipError_t launch_log_reset(DevLog* log, hipStream_t s);
 

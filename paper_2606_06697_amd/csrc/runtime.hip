@@ -500,6 +500,18 @@ static bool policy_ok(int policy) {
     return policy == AGILE_POLICY_SUPPRESS_LOG || policy == AGILE_POLICY_SUPPRESS_ONLY;
 }
 
+// Binding of a pointer argument of a guarded call: the USER range containing p, from the host
+// copy of the table (the state the launch is ordered after), or the empty interval.
+static Bind host_bind(const agile_rt* rt, uint64_t p) {
+    const auto& e = rt->entries;
+    auto it = std::upper_bound(e.begin(), e.end(), p,
+                               [](uint64_t a, const Entry& x) { return a < x.base; });
+    if (it == e.begin()) return Bind{0, 0};
+    --it;
+    if (p < it->end && it->kind == AGILE_KIND_USER) return Bind{it->base, it->end};
+    return Bind{0, 0};
+}
+
 int agile_guarded_copy(agile_rt* rt, void* d_dst, const void* d_src, uint64_t nbytes, int policy,
                        void* stream) {
     if (!rt || !policy_ok(policy)) return AGILE_EINVAL;
@@ -509,7 +521,8 @@ int agile_guarded_copy(agile_rt* rt, void* d_dst, const void* d_src, uint64_t nb
     int rc = prepare(rt, s);
     if (rc != AGILE_OK) return rc;
     const unsigned long long seq = rt->seq++;
-    if (launch_copy(true, rt->tab, rt->d_log, d_dst, d_src, nbytes, seq,
+    const Bind b[2] = {host_bind(rt, (uint64_t)d_src), host_bind(rt, (uint64_t)d_dst)};
+    if (launch_copy(true, rt->tab, rt->d_log, b, d_dst, d_src, nbytes, seq,
                     policy == AGILE_POLICY_SUPPRESS_LOG, rt->info, s) != hipSuccess)
         return AGILE_EDEVICE;
     return AGILE_OK;
@@ -526,7 +539,9 @@ int agile_guarded_triad(agile_rt* rt, float* d_a, const float* d_b, const float*
     int rc = prepare(rt, s);
     if (rc != AGILE_OK) return rc;
     const unsigned long long seq = rt->seq++;
-    if (launch_triad(true, rt->tab, rt->d_log, d_a, d_b, d_c, s_, n, seq,
+    const Bind b[3] = {host_bind(rt, (uint64_t)d_b), host_bind(rt, (uint64_t)d_c),
+                       host_bind(rt, (uint64_t)d_a)};
+    if (launch_triad(true, rt->tab, rt->d_log, b, d_a, d_b, d_c, s_, n, seq,
                      policy == AGILE_POLICY_SUPPRESS_LOG, rt->info, s) != hipSuccess)
         return AGILE_EDEVICE;
     return AGILE_OK;
@@ -556,7 +571,9 @@ int agile_guarded_gather(agile_rt* rt, void* d_out, const void* d_table, uint64_
     rc = prepare(rt, s);
     if (rc != AGILE_OK) return rc;
     const unsigned long long seq = rt->seq++;
-    if (launch_gather(true, rt->tab, rt->d_log, d_out, d_table, row_bytes, d_idx, n, w, seq,
+    const Bind b[3] = {host_bind(rt, (uint64_t)d_idx), host_bind(rt, (uint64_t)d_table),
+                       host_bind(rt, (uint64_t)d_out)};
+    if (launch_gather(true, rt->tab, rt->d_log, b, d_out, d_table, row_bytes, d_idx, n, w, seq,
                       policy == AGILE_POLICY_SUPPRESS_LOG, rt->info, s) != hipSuccess)
         return AGILE_EDEVICE;
     return AGILE_OK;
@@ -576,7 +593,9 @@ int agile_guarded_scatter(agile_rt* rt, void* d_dst, uint64_t row_bytes, const i
     rc = prepare(rt, s);
     if (rc != AGILE_OK) return rc;
     const unsigned long long seq = rt->seq++;
-    if (launch_scatter(true, rt->tab, rt->d_log, d_dst, row_bytes, d_idx, d_src, n, w, accumulate,
+    const Bind b[3] = {host_bind(rt, (uint64_t)d_idx), host_bind(rt, (uint64_t)d_src),
+                       host_bind(rt, (uint64_t)d_dst)};
+    if (launch_scatter(true, rt->tab, rt->d_log, b, d_dst, row_bytes, d_idx, d_src, n, w, accumulate,
                        seq, policy == AGILE_POLICY_SUPPRESS_LOG, rt->info, s) != hipSuccess)
         return AGILE_EDEVICE;
     return AGILE_OK;
@@ -771,7 +790,7 @@ static DevInfo current_info() {
 
 int agile_unguarded_copy(void* d_dst, const void* d_src, uint64_t nbytes, void* stream) {
     if (nbytes && (!d_dst || !d_src)) return AGILE_EINVAL;
-    return launch_copy(false, DevTable{}, nullptr, d_dst, d_src, nbytes, 0, 0, current_info(),
+    return launch_copy(false, DevTable{}, nullptr, nullptr, d_dst, d_src, nbytes, 0, 0, current_info(),
                        static_cast<hipStream_t>(stream)) == hipSuccess
                ? AGILE_OK
                : AGILE_EDEVICE;
@@ -781,7 +800,7 @@ int agile_unguarded_triad(float* d_a, const float* d_b, const float* d_c, float 
                           void* stream) {
     if (n && (!d_a || !d_b || !d_c)) return AGILE_EINVAL;
     if (((uint64_t)d_a | (uint64_t)d_b | (uint64_t)d_c) & 3) return AGILE_EINVAL;
-    return launch_triad(false, DevTable{}, nullptr, d_a, d_b, d_c, s_, n, 0, 0, current_info(),
+    return launch_triad(false, DevTable{}, nullptr, nullptr, d_a, d_b, d_c, s_, n, 0, 0, current_info(),
                         static_cast<hipStream_t>(stream)) == hipSuccess
                ? AGILE_OK
                : AGILE_EDEVICE;
@@ -793,7 +812,7 @@ int agile_unguarded_gather(void* d_out, const void* d_table, uint64_t row_bytes,
     int rc = rows_args_ok(row_bytes, n, dtype, d_out, d_table, &w);
     if (rc != AGILE_OK) return rc;
     if (n && (!d_out || !d_table || !d_idx)) return AGILE_EINVAL;
-    return launch_gather(false, DevTable{}, nullptr, d_out, d_table, row_bytes, d_idx, n, w, 0, 0,
+    return launch_gather(false, DevTable{}, nullptr, nullptr, d_out, d_table, row_bytes, d_idx, n, w, 0, 0,
                          current_info(), static_cast<hipStream_t>(stream)) == hipSuccess
                ? AGILE_OK
                : AGILE_EDEVICE;
@@ -807,7 +826,7 @@ int agile_unguarded_scatter(void* d_dst, uint64_t row_bytes, const int64_t* d_id
     int rc = rows_args_ok(row_bytes, n, dtype, d_dst, d_src, &w);
     if (rc != AGILE_OK) return rc;
     if (n && (!d_dst || !d_src || !d_idx)) return AGILE_EINVAL;
-    return launch_scatter(false, DevTable{}, nullptr, d_dst, row_bytes, d_idx, d_src, n, w,
+    return launch_scatter(false, DevTable{}, nullptr, nullptr, d_dst, row_bytes, d_idx, d_src, n, w,
                           accumulate, 0, 0, current_info(),
                           static_cast<hipStream_t>(stream)) == hipSuccess
                ? AGILE_OK

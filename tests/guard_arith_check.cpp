@@ -81,6 +81,44 @@ int main() {
                   (unsigned long long)k);
         }
     }
+    // rows that the row kernels take on their fast path: the index element and the whole
+    // contiguous-operand row are inside their bindings for every row below nfast, and row
+    // nfast (when < n) fails one of the two
+    for (int it = 0; it < 200000; ++it) {
+        auto mkbind = [&](uint64_t& p) {
+            uint64_t lo = pick_u64(), hi = pick_u64();
+            if (lo > hi) { uint64_t t = lo; lo = hi; hi = t; }
+            if (rng() % 3 == 0) hi = lo + rng() % 100000;
+            if (hi < lo) hi = ~0ull;
+            Bind b{lo, hi};
+            if (rng() % 10 == 0) b = Bind{0, 0};
+            p = (rng() % 4 != 0 && b.hi > b.lo) ? b.lo + rng() % (b.hi - b.lo) : pick_u64();
+            return b;
+        };
+        uint64_t pi, pc, pr;
+        const Bind bi = mkbind(pi), bc = mkbind(pc), br = mkbind(pr);
+        const uint32_t W = widths[rng() % 2];
+        const uint64_t rb = W * (1 + rng() % 64);
+        const uint64_t n = rng() % 50000;
+        const RowsGuard r = rows_guard(bi, bc, br, pi, pc, pr, n, rb, W);
+        CHECK(r.nfast <= n, "nfast > n");
+        auto row_ok = [&](uint64_t i) {
+            const i128 Ai = (i128)pi + (i128)(8 * i);
+            const bool iok = bi.hi > bi.lo && pi >= bi.lo && pi < bi.hi && Ai >= (i128)bi.lo &&
+                             Ai + 8 <= (i128)bi.hi;
+            const i128 Ac = (i128)pc + (i128)i * (i128)rb;
+            const bool cok = bc.hi > bc.lo && pc >= bc.lo && pc < bc.hi && Ac >= (i128)bc.lo &&
+                             Ac + (i128)rb <= (i128)bc.hi;
+            return iok && cok;
+        };
+        for (uint64_t i : {(uint64_t)0, r.nfast > 0 ? r.nfast - 1 : 0, r.nfast / 2}) {
+            if (i < r.nfast) CHECK(row_ok(i), "row %llu below nfast not allowed", (unsigned long long)i);
+        }
+        if (r.nfast < n) CHECK(!row_ok(r.nfast), "row nfast=%llu allowed", (unsigned long long)r.nfast);
+        const RowsGuard o = rows_open(n, rb, W);
+        CHECK(o.nfast == n && o.ki == n && o.kc == n * (rb / W) && o.g.rlo == INT64_MIN &&
+              o.g.rhi == INT64_MAX, "rows_open");
+    }
     if (fails) { printf("FAILED %d\n", fails); return 1; }
     printf("ok\n");
     return 0;
