@@ -45,6 +45,9 @@ def parse():
                    help="skip the embedding and batched-launch measurements")
     p.add_argument("--serve-seconds", type=float, default=5.0,
                    help="length of the serving-loop run (0 skips it)")
+    p.add_argument("--counters-pass", action="store_true",
+                   help="only launch each large-table kernel a few times, plus a plain 1 GiB copy "
+                        "(the reference for scaling HBM counters), for a rocprofv3 --pmc run")
     p.add_argument("--queries-log2", type=int, default=28, help=argparse.SUPPRESS)
     return p.parse_args()
 
@@ -108,6 +111,21 @@ def main():
     bytes_triad = TRIAD_N * 12
     bytes_gather = GATHER_N * 16
     step_bytes = bytes_validate + bytes_triad + bytes_gather
+
+    if args.counters_pass:
+        for _ in range(3):
+            g.agile_validate_ptrs(vt.handle, q, nq, verdict, owner)
+            g.agile_guarded_triad(dt.handle, a, b, c, 3.0, TRIAD_N)
+            g.agile_unguarded_triad(a_ref, b, c, 3.0, TRIAD_N)
+            g.agile_guarded_gather(dt.handle, out, table, 4, idx, GATHER_N)
+            g.agile_unguarded_gather(out_ref, table, 4, idx, GATHER_N)
+            g.agile_unguarded_copy(a_ref, b, 4 * TRIAD_N)      # reference: 1 GiB in, 1 GiB out
+        dt.fault_log(clear=True)
+        torch.cuda.synchronize()
+        print(json.dumps({"counters_pass": True, "bytes_per_launch": {
+            "validate": nq * 21, "triad": TRIAD_N * 12, "gather": GATHER_N * 16,
+            "copy_reference": {"read": 4 * TRIAD_N, "write": 4 * TRIAD_N}}}), flush=True)
+        return
 
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     t_kern = {"validate": [], "triad": [], "gather": []}
