@@ -312,9 +312,8 @@ def _gather_bytes(mem, bind, p, roff, rows, c0, c1, D, w):
     rel = np.array([int(roff[r]) + (p - bind[0]) + o if c1[r] > c0[r] else 0 for r in rows],
                    dtype=np.int64)
     full = (c0[rows] == 0) & (c1[rows] == D)
-    if full.any():
-        fi = np.flatnonzero(full)
-        out[fi] = arr[rel[fi][:, None] + np.arange(D * w)[None, :]]
+    for k in np.flatnonzero(full):
+        out[k] = arr[rel[k]:rel[k] + D * w]
     for k in np.flatnonzero(~full):
         r = rows[k]
         for col in range(c0[r], c1[r]):
@@ -330,20 +329,28 @@ def _scatter_store(mem, bind, p, roff, rows, c0, c1, D, w, data, accumulate):
     arr, o = mem.locate(bind[0], bind[1])
     dt = _DT[w]
     if accumulate:
-        # fp64 accumulation of all contributions per destination element, then one rounding.
-        acc = {}
+        # Every allowed (row, column) contribution lands on one destination element; each
+        # element becomes its old value plus the float64 sum of its contributions, rounded once
+        # to the element type (the order of the float64 additions is not significant at the
+        # tolerance the gradient is held to).
+        offs, vals = [], []
         for k, r in enumerate(rows):
             base = int(roff[r]) + (p - bind[0]) + o
-            vals = data[k].view(dt)
-            for col in range(c0[r], c1[r]):
-                s = base + col * w
-                acc.setdefault(s, []).append(float(vals[col]))
-        for s, lst in acc.items():
-            old = float(arr[s:s + w].view(dt)[0])
-            tot = np.float64(old)
-            for v in lst:
-                tot = tot + np.float64(v)
-            arr[s:s + w] = np.array([tot], dtype=dt).view(np.uint8)
+            cols = np.arange(c0[r], c1[r], dtype=np.int64)
+            offs.append(base + cols * w)
+            vals.append(data[k].view(dt)[c0[r]:c1[r]].astype(np.float64))
+        if not offs:
+            return
+        offs = np.concatenate(offs)
+        vals = np.concatenate(vals)
+        order = np.argsort(offs, kind="stable")
+        so, sv = offs[order], vals[order]
+        starts = np.flatnonzero(np.r_[True, so[1:] != so[:-1]])
+        uniq = so[starts]
+        sums = np.add.reduceat(sv, starts)
+        byte_idx = uniq[:, None] + np.arange(w, dtype=np.int64)[None, :]
+        old = arr[byte_idx].reshape(-1).view(dt).astype(np.float64)
+        arr[byte_idx] = (old + sums).astype(dt).view(np.uint8).reshape(-1, w)
         return
     for k, r in enumerate(rows):
         base = int(roff[r]) + (p - bind[0]) + o
