@@ -80,11 +80,10 @@ struct DevLog {
     uint32_t first_verdict;
     int32_t first_owner;
     uint32_t reserved;
-    // scratch used inside one guarded launch, returned to its idle state by the launch's
-    // last workgroup
+    // scratch of one guarded launch, returned to its idle state by the launch's finishing kernel
     unsigned long long s_minkey;   // min over (elem << 2 | operand) of this launch's denials
     unsigned long long s_count;    // denials of this launch
-    unsigned int s_done;           // workgroups finished
+    unsigned int s_done;           // unused (kept for the layout)
     unsigned int s_pad;
 };
 
@@ -238,40 +237,18 @@ struct FaultAcc {
     }
 };
 
-// Fold per-lane denials into the log; the last workgroup writes the smallest key's record.
-template <typename Payload>
-__device__ inline void fold_faults(FaultAcc acc, DevLog* log, const Payload& payload) {
-    __shared__ unsigned int s_last;
+// Fold per-lane denials into the launch's scratch: one atomic pair per wave that saw a denial
+// (no workgroup-wide step, so waves and workgroups finish independently). The record of the
+// smallest key is written afterwards by the launch's finishing kernel.
+__device__ inline void fold_faults(FaultAcc acc, DevLog* log) {
     const unsigned long long c = wave_sum_u64(acc.cnt);
     const unsigned long long m = wave_min_u64(acc.mk);
     if ((threadIdx.x & 63u) == 0 && c) {
         atomicAdd(&log->s_count, c);
         atomicMin(&log->s_minkey, m);
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned int ticket = atomicAdd(&log->s_done, 1u);
-        s_last = ticket == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (s_last && threadIdx.x == 0) {
-        __threadfence();
-        const unsigned long long total = atomicAdd(&log->s_count, 0ull);
-        const unsigned long long key = atomicMin(&log->s_minkey, ~0ull);
-        if (total) {
-            atomicAdd(&log->count, total);
-            payload(key);
-        }
-        log->s_count = 0;
-        log->s_minkey = ~0ull;
-        log->s_done = 0;
-        __threadfence();
-    }
 }
 
-// Out of line: runs once per launch (last workgroup), so it should not add to the registers of
-// the kernels' main loops.
 __device__ inline void record_at(const DevTable& t, DevLog* log, unsigned long long seq,
                                  unsigned long long elem, uint32_t operand, __int128 A, uint32_t w,
                                  uint32_t op) {
@@ -281,5 +258,17 @@ __device__ inline void record_at(const DevTable& t, DevLog* log, unsigned long l
     if (in_space) reason_lane(t, (uint64_t)A, w, v, o);
     log_record(log, seq, elem, operand, (uint64_t)A, w, op, v, o);
 }
+
+// Where the denials of a row kernel (gather, scatter, scatter-add) live: a key's element e is
+// row i = e / D, column e % D; operand 0 is the index load at idx + 8 i, the contiguous operand is
+// at cont + e * w and the row-addressed one at rowp + idx[i] * rb + column * w.
+struct FaultSite {
+    uint32_t op;           // AGILE_OP_* of the call
+    uint32_t w;            // element width
+    uint32_t row_operand;  // operand number of the row-addressed pointer (1 gather, 2 scatter)
+    uint32_t pad;
+    uint64_t D, rb, ki;    // elements per row, row bytes, readable index prefix
+    uint64_t idx, cont, rowp;
+};
 
 }  // namespace agile

@@ -7,8 +7,8 @@
 // interval [rlo, rhi] of rows that lie wholly inside the allocation, so the per-row guard is
 // two signed compares of the loaded index against scalars. Rows outside it (hostile indices, or a table pointer that is not
 // row-aligned with its allocation's ends) take an exact 128-bit per-element path. Denials are
-// counted per lane, reduced per wave, and folded into the handle's log: the smallest
-// (element, operand) key wins, and the last workgroup to finish writes that denial's record.
+// counted per lane, reduced per wave and folded into the handle's log (count and smallest
+// (element, operand) key); a one-thread kernel after the launch writes that denial's record.
 // GUARD=false compiles the same loops with no binding and no compare (the unguarded twin).
 #include "launch.h"
 
@@ -130,25 +130,7 @@ __global__ __launch_bounds__(GBLOCK) void k_gather(DevTable t, DevLog* log, uint
             }
         }
     }
-    if (GUARD && logon) {
-        fold_faults(acc, log, [&](unsigned long long key) {
-            const unsigned long long elem = key >> 2;
-            const uint32_t operand = (uint32_t)(key & 3u);
-            const uint64_t i = elem / D, col = elem % D;
-            __int128 A;
-            uint32_t w = W;
-            if (operand == 0) {
-                A = (__int128)(uint64_t)idx + (__int128)(8 * i);
-                w = 8;
-            } else if (operand == 1) {
-                const int64_t v = i < Ki ? idx[i] : 0;
-                A = (__int128)(uint64_t)T + (__int128)v * (__int128)rb + (__int128)(col * W);
-            } else {
-                A = (__int128)(uint64_t)out + (__int128)elem * W;
-            }
-            record_at(t, log, seq, elem, operand, A, w, 3 /*OP_GATHER*/);
-        });
-    }
+    if (GUARD && logon) fold_faults(acc, log);
 }
 
 // Plain scatter (no accumulation): with duplicate indices one of the writers wins.
@@ -215,25 +197,7 @@ __global__ __launch_bounds__(GBLOCK) void k_scatter(DevTable t, DevLog* log, uin
             }
         }
     }
-    if (GUARD && logon) {
-        fold_faults(acc, log, [&](unsigned long long key) {
-            const unsigned long long elem = key >> 2;
-            const uint32_t operand = (uint32_t)(key & 3u);
-            const uint64_t i = elem / D, col = elem % D;
-            __int128 A;
-            uint32_t w = W;
-            if (operand == 0) {
-                A = (__int128)(uint64_t)idx + (__int128)(8 * i);
-                w = 8;
-            } else if (operand == 1) {
-                A = (__int128)(uint64_t)src + (__int128)elem * W;
-            } else {
-                const int64_t v = i < Ki ? idx[i] : 0;
-                A = (__int128)(uint64_t)dst + (__int128)v * (__int128)rb + (__int128)(col * W);
-            }
-            record_at(t, log, seq, elem, operand, A, w, 4 /*OP_SCATTER*/);
-        });
-    }
+    if (GUARD && logon) fold_faults(acc, log);
 }
 
 __global__ void k_log_reset(DevLog* log) {
@@ -256,6 +220,55 @@ __global__ void k_log_reset(DevLog* log) {
 hipError_t launch_log_reset(DevLog* log, hipStream_t s) {
     hipLaunchKernelGGL(k_log_reset, dim3(1), dim3(1), 0, s, log);
     return hipGetLastError();
+}
+
+// Finishing step of a row kernel's launch: adds the launch's denial count to the log and, if
+// the log holds no record yet, records the smallest key (its address and reason).
+__global__ void k_fault_finish(DevTable t, DevLog* log, FaultSite f, unsigned long long seq) {
+    // device-scope atomics: the launch's waves folded into these from every XCD
+    const unsigned long long total = atomicAdd(&log->s_count, 0ull);
+    if (total == 0) return;
+    const unsigned long long key = atomicMin(&log->s_minkey, ~0ull);
+    atomicAdd(&log->count, total);
+    const unsigned long long elem = key >> 2;
+    const uint32_t operand = (uint32_t)(key & 3u);
+    const uint64_t i = elem / f.D, col = elem % f.D;
+    const int64_t* idx = reinterpret_cast<const int64_t*>(f.idx);
+    __int128 A;
+    uint32_t w = f.w;
+    if (operand == 0) {
+        A = (__int128)f.idx + (__int128)(8 * i);
+        w = 8;
+    } else if (operand == f.row_operand) {
+        const int64_t v = i < f.ki ? idx[i] : 0;
+        A = (__int128)f.rowp + (__int128)v * (__int128)f.rb + (__int128)(col * f.w);
+    } else {
+        A = (__int128)f.cont + (__int128)elem * f.w;
+    }
+    record_at(t, log, seq, elem, operand, A, w, f.op);
+    atomicExch(&log->s_count, 0ull);
+    atomicExch(&log->s_minkey, ~0ull);
+}
+
+hipError_t launch_fault_finish(const DevTable& t, DevLog* log, const FaultSite& f,
+                               unsigned long long seq, hipStream_t s) {
+    hipLaunchKernelGGL(k_fault_finish, dim3(1), dim3(1), 0, s, t, log, f, seq);
+    return hipGetLastError();
+}
+
+FaultSite rows_fault_site(uint32_t op, uint32_t w, uint32_t row_operand, uint64_t rb, uint64_t ki,
+                          const void* idx, const void* cont, const void* rowp) {
+    FaultSite f{};
+    f.op = op;
+    f.w = w;
+    f.row_operand = row_operand;
+    f.D = rb / w;
+    f.rb = rb;
+    f.ki = ki;
+    f.idx = (uint64_t)idx;
+    f.cont = (uint64_t)cont;
+    f.rowp = (uint64_t)rowp;
+    return f;
 }
 
 // Lanes per row: enough to cover the row's chunks, at most a wave.
@@ -316,6 +329,9 @@ hipError_t launch_gather(bool guard, const DevTable& t, DevLog* log, const Bind*
                                         (uint64_t)tab, n, rb, w);
         if (w == 4) gather_w<true, 4>(t, log, out, tab, rb, idx, n, rg, seq, logon, d, s);
         else gather_w<true, 8>(t, log, out, tab, rb, idx, n, rg, seq, logon, d, s);
+        if (logon)
+            return launch_fault_finish(t, log, rows_fault_site(3 /*OP_GATHER*/, w, 1, rb, rg.ki, idx,
+                                                                 out, tab), seq, s);
     } else {
         const RowsGuard rg = rows_open(n, rb, w);
         if (w == 4) gather_w<false, 4>(t, log, out, tab, rb, idx, n, rg, seq, logon, d, s);
@@ -356,16 +372,20 @@ static void scatter_w(const DevTable& t, DevLog* log, void* dst, uint64_t rb, co
 
 hipError_t launch_scatter(bool guard, const DevTable& t, DevLog* log, const Bind* binds, void* dst,
                           uint64_t rb, const int64_t* idx, const void* src, uint64_t n, uint32_t w,
-                          int accumulate, unsigned long long seq, int logon, const DevInfo& d,
-                          hipStream_t s) {
+                          int accumulate, unsigned long long seq, int logon, void* scratch,
+                          const DevInfo& d, hipStream_t s) {
     if (n == 0) return hipSuccess;
     if (accumulate)
-        return launch_scatter_add(guard, t, log, binds, dst, rb, idx, src, n, w, seq, logon, d, s);
+        return launch_scatter_add(guard, t, log, binds, dst, rb, idx, src, n, w, seq, logon,
+                                  scratch, d, s);
     if (guard) {
         const RowsGuard rg = rows_guard(binds[0], binds[1], binds[2], (uint64_t)idx, (uint64_t)src,
                                         (uint64_t)dst, n, rb, w);
         if (w == 4) scatter_w<true, 4>(t, log, dst, rb, idx, src, n, rg, seq, logon, d, s);
         else scatter_w<true, 8>(t, log, dst, rb, idx, src, n, rg, seq, logon, d, s);
+        if (logon)
+            return launch_fault_finish(t, log, rows_fault_site(4 /*OP_SCATTER*/, w, 2, rb, rg.ki, idx,
+                                                                 src, dst), seq, s);
     } else {
         const RowsGuard rg = rows_open(n, rb, w);
         if (w == 4) scatter_w<false, 4>(t, log, dst, rb, idx, src, n, rg, seq, logon, d, s);

@@ -1,16 +1,25 @@
 // Guarded scatter-add dst[idx[i], :] += src[i, :] (kernel memory guard of AgileOS Section V-E),
 // organised so that heavily repeated destination rows (the hot rows of a Zipf-distributed
-// embedding gradient) do not serialize on atomics.
+// embedding gradient) neither serialize on atomics nor pay one atomic row-update per index.
 //
-// Each workgroup takes a chunk of 2048 consecutive indices, sorts (destination key, position)
-// pairs in LDS with a bitonic network, and cuts the sorted chunk into pieces of at most 32
-// equal keys. A wave sums one piece's source rows in position order (fixed order, fp32 or fp64
-// registers) and adds the sum to the destination row with one atomic per element, so a row
-// repeated r times in a chunk costs ceil(r/32) atomic row-updates instead of r. The guard binds
-// the three pointer arguments once per wave: index loads and source elements are prefix-bounded,
-// destination rows inside the binding's row interval take the fast path, every other row is
-// checked per element with exact arithmetic. Denials are counted and the smallest (element,
-// operand) key is recorded as in the other data-dependent guarded kernels.
+// Sorted path (large calls). Rows that pass the guard's fast test (index readable, source row
+// wholly inside its allowed prefix, destination row inside the binding's row interval) get a
+// 32-bit key, their destination row's offset inside that interval; every other row gets the
+// largest key. A stable LSD radix sort (8-bit digits; per pass: per-tile digit histograms, one
+// workgroup's exclusive scan, a stable scatter ranked with wave ballots; a pass whose digit is the
+// same for every key is skipped on the device) orders (key, position) pairs by destination row,
+// position ascending. Each wave then walks a tile of 256 sorted entries and sums the source rows
+// of each run of equal keys in position order; a run that lies wholly inside the tile owns its
+// destination row and adds with a plain read-modify-write, a run that crosses a tile boundary
+// adds with one atomic per element. Rows that failed the fast test follow in a separate kernel
+// that checks every element exactly (denied loads read zero, denied stores are dropped) and
+// counts denials as the other data-dependent guarded kernels do; a one-thread kernel after the
+// launch records the smallest key.
+//
+// Chunk path (small calls, or destination intervals too large for 32-bit keys): each workgroup
+// takes 2048 consecutive indices, sorts (key, position) pairs in LDS with a bitonic network,
+// cuts the sorted chunk into pieces of at most 32 equal keys, sums each piece in position order
+// and adds the sum with one atomic per element; rows outside the interval are checked per element.
 #include <type_traits>
 
 #include "launch.h"
@@ -190,24 +199,431 @@ __global__ __launch_bounds__(SABLOCK) void k_scatter_add(DevTable t, DevLog* log
         }
         __syncthreads();
     }
-    if (GUARD && logon) {
-        fold_faults(acc, log, [&](unsigned long long k) {
-            const unsigned long long elem = k >> 2;
-            const uint32_t operand = (uint32_t)(k & 3u);
-            const uint64_t i = elem / D, col = elem % D;
-            __int128 A;
-            uint32_t w = W;
-            if (operand == 0) {
-                A = (__int128)(uint64_t)idx + (__int128)(8 * i);
-                w = 8;
-            } else if (operand == 1) {
-                A = (__int128)(uint64_t)src + (__int128)elem * W;
+    if (GUARD && logon) fold_faults(acc, log);
+}
+
+// ================================================================ sorted path
+constexpr int SRT_BLOCK = 256;
+constexpr uint32_t SRT_TILE = 4096;   // keys per histogram / scatter tile (16 per thread)
+constexpr uint32_t SRT_KPT = SRT_TILE / SRT_BLOCK;
+constexpr uint32_t SRT_SENT = 0xFFFFFFFFu;
+constexpr uint32_t RED_TILE = 256;    // sorted entries per reduce wave
+// ctl[p] (p < 4): pass p was skipped (one digit value only); ctl[4 + p]: buffer pass p reads,
+// ctl[8 + p]: the buffer the reduce reads when the sort has p passes
+constexpr int CTL_WORDS = 16;
+
+struct SortBufs {
+    uint32_t* keys[2];
+    uint32_t* vals[2];
+    uint32_t* hist;  // [256 * ntiles], scanned in place
+    uint32_t* ctl;   // [CTL_WORDS]
+    uint64_t* slow;  // [ceil(n / 64)]: bit l of word w marks row 64 w + l as failing the fast test
+};
+
+static inline uint64_t srt_ntiles(uint64_t n) { return (n + SRT_TILE - 1) / SRT_TILE; }
+
+size_t scatter_add_scratch_bytes(uint64_t n) {
+    const uint64_t a = ((n * 4 + 255) / 256) * 256;
+    return 4 * a + srt_ntiles(n) * 256 * 4 + 256 + ((n + 63) / 64) * 8;
+}
+
+static SortBufs sort_bufs(void* scratch, uint64_t n) {
+    const uint64_t a = ((n * 4 + 255) / 256) * 256;
+    uint8_t* p = static_cast<uint8_t*>(scratch);
+    SortBufs b;
+    b.keys[0] = reinterpret_cast<uint32_t*>(p);
+    b.keys[1] = reinterpret_cast<uint32_t*>(p + a);
+    b.vals[0] = reinterpret_cast<uint32_t*>(p + 2 * a);
+    b.vals[1] = reinterpret_cast<uint32_t*>(p + 3 * a);
+    b.hist = reinterpret_cast<uint32_t*>(p + 4 * a);
+    b.ctl = reinterpret_cast<uint32_t*>(p + 4 * a + srt_ntiles(n) * 256 * 4);
+    b.slow = reinterpret_cast<uint64_t*>(p + 4 * a + srt_ntiles(n) * 256 * 4 + 256);
+    return b;
+}
+
+// Keys: guarded rows that pass the fast test get (idx - rlo); the others the sentinel. The
+// unguarded twin keys every row by idx + 2^31 (its indices must lie in [-2^31, 2^31 - 1)).
+template <bool GUARD>
+__global__ __launch_bounds__(SRT_BLOCK) void k_srt_keys(const int64_t* __restrict__ idx, uint64_t n,
+                                                        RowsGuard rg, SortBufs b) {
+    const uint64_t tid = (uint64_t)blockIdx.x * SRT_BLOCK + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * SRT_BLOCK;
+    if (tid < CTL_WORDS) b.ctl[tid] = 0;  // every pass starts from buffer 0
+    // the loop bound is uniform per wave (i0 is the wave's first row), so ballots see all lanes
+    for (uint64_t i0 = tid & ~63ull; i0 < n; i0 += stride) {
+        const uint64_t i = i0 + (threadIdx.x & 63u);
+        uint32_t key = SRT_SENT;
+        bool slow = false;
+        if (i < n) {
+            if (GUARD) {
+                const int64_t x = i < rg.nfast ? idx[i] : 0;
+                const bool fast = i < rg.nfast && rg.g.rlo <= x && x <= rg.g.rhi;
+                key = fast ? (uint32_t)((uint64_t)x - (uint64_t)rg.g.rlo) : SRT_SENT;
+                slow = !fast;
             } else {
-                const int64_t v = i < Ki ? idx[i] : 0;
-                A = (__int128)(uint64_t)dst + (__int128)v * (__int128)rb + (__int128)(col * W);
+                key = (uint32_t)((uint64_t)idx[i] + 0x80000000ull);
             }
-            record_at(t, log, seq, elem, operand, A, w, 5 /*OP_SCATTER_ADD*/);
-        });
+            b.keys[0][i] = key;
+            b.vals[0][i] = (uint32_t)i;
+        }
+        if (GUARD) {
+            const uint64_t m = __ballot(slow);
+            if ((threadIdx.x & 63u) == 0) b.slow[i0 >> 6] = m;
+        }
+    }
+}
+
+__global__ __launch_bounds__(SRT_BLOCK) void k_srt_hist(SortBufs b, uint64_t n, uint32_t pass) {
+    __shared__ uint32_t h[256];
+    const uint32_t tid = threadIdx.x, shift = 8 * pass;
+    const uint32_t* keys = b.keys[b.ctl[4 + pass]];
+    h[tid] = 0;
+    __syncthreads();
+    const uint64_t t0 = (uint64_t)blockIdx.x * SRT_TILE;
+#pragma unroll 4
+    for (uint32_t k = 0; k < SRT_KPT; ++k) {
+        const uint64_t i = t0 + k * SRT_BLOCK + tid;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    b.hist[(uint64_t)tid * gridDim.x + blockIdx.x] = h[tid];
+}
+
+// One workgroup: exclusive scan of the digit-major histogram (each wave scans one contiguous
+// segment with coalesced loads: a sum pass, a scan of the wave totals, a write pass), then the
+// skip flag of the pass (a digit holding all n keys) and the buffer the next pass reads.
+constexpr int SCAN_BLOCK = 1024;
+__global__ __launch_bounds__(SCAN_BLOCK) void k_srt_scan(SortBufs b, uint64_t n, uint32_t ntiles,
+                                                         uint32_t pass) {
+    constexpr uint32_t NW = SCAN_BLOCK / 64;
+    __shared__ uint32_t wsum[NW];
+    __shared__ uint32_t skip;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+    const uint64_t E = (uint64_t)ntiles * 256;
+    const uint64_t seg = (((E + NW - 1) / NW) + 63) / 64 * 64;
+    const uint64_t lo = wv * seg < E ? wv * seg : E, hi = lo + seg < E ? lo + seg : E;
+    if (tid == 0) skip = 0;
+    constexpr int SCH = 32;
+    uint32_t s = 0;
+    for (uint64_t c0 = lo; c0 < hi; c0 += 64 * SCH) {
+        uint32_t v[SCH];
+#pragma unroll
+        for (int j = 0; j < SCH; ++j) {
+            const uint64_t e = c0 + (uint64_t)j * 64 + lane;
+            v[j] = e < hi ? b.hist[e] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < SCH; ++j) s += v[j];
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) wsum[wv] = s;
+    __syncthreads();
+    uint32_t carry = 0;
+    for (uint32_t k = 0; k < wv; ++k) carry += wsum[k];
+    // write pass in blocks of SCH groups: all SCH loads are issued before the first store
+    for (uint64_t c0 = lo; c0 < hi; c0 += 64 * SCH) {
+        uint32_t v[SCH];
+#pragma unroll
+        for (int j = 0; j < SCH; ++j) {
+            const uint64_t e = c0 + (uint64_t)j * 64 + lane;
+            v[j] = e < hi ? b.hist[e] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < SCH; ++j) {
+            const uint64_t e = c0 + (uint64_t)j * 64 + lane;
+            uint32_t inc = v[j];
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(inc, o, 64);
+                if (lane >= (uint32_t)o) inc += y;
+            }
+            if (e < hi) b.hist[e] = carry + inc - v[j];
+            carry += __shfl(inc, 63, 64);
+        }
+    }
+    __syncthreads();
+    // a digit's count is the difference of consecutive digit starts
+    if (tid < 256) {
+        const uint32_t a = b.hist[(uint64_t)tid * ntiles];
+        const uint64_t nxt = tid < 255 ? (uint64_t)b.hist[(uint64_t)(tid + 1) * ntiles] : n;
+        if (nxt - a == n) skip = 1;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const uint32_t src = b.ctl[4 + pass];
+        b.ctl[pass] = skip;
+        b.ctl[4 + pass + 1] = skip ? src : 1u - src;
+    }
+}
+
+// Stable scatter of one pass: items are taken in rounds of 256 consecutive positions; inside a
+// round, wave ballots rank equal digits by lane, per-wave digit counts rank them across waves, and
+// a running per-digit count carries the order from round to round.
+__global__ __launch_bounds__(SRT_BLOCK) void k_srt_scatter(SortBufs b, uint64_t n, uint32_t pass) {
+    if (b.ctl[pass]) return;
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wcnt[SRT_BLOCK / 64][256];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6, shift = 8 * pass;
+    const uint32_t src = b.ctl[4 + pass];
+    const uint32_t* kin = b.keys[src];
+    const uint32_t* vin = b.vals[src];
+    uint32_t* kout = b.keys[1u - src];
+    uint32_t* vout = b.vals[1u - src];
+    run[tid] = b.hist[(uint64_t)tid * gridDim.x + blockIdx.x];
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const uint64_t t0 = (uint64_t)blockIdx.x * SRT_TILE;
+    for (uint32_t k = 0; k < SRT_KPT; ++k) {
+#pragma unroll
+        for (int w = 0; w < SRT_BLOCK / 64; ++w) wcnt[w][tid] = 0;
+        __syncthreads();
+        const uint64_t i = t0 + k * SRT_BLOCK + tid;
+        const bool valid = i < n;
+        const uint32_t key = valid ? kin[i] : 0u;
+        const uint32_t val = valid ? vin[i] : 0u;
+        const uint32_t d = (key >> shift) & 255u;
+        uint64_t match = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const uint64_t bb = __ballot((d >> bit) & 1u);
+            match &= ((d >> bit) & 1u) ? bb : ~bb;
+        }
+        const uint32_t rank = (uint32_t)__popcll(match & below);
+        if (valid && rank == 0) wcnt[wv][d] = (uint32_t)__popcll(match);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = run[d] + rank;
+            for (uint32_t w = 0; w < wv; ++w) pos += wcnt[w][d];
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+#pragma unroll
+        for (int w = 0; w < SRT_BLOCK / 64; ++w) add += wcnt[w][tid];
+        run[tid] += add;
+        __syncthreads();
+    }
+}
+
+template <int W, int EPL>
+struct RowVec {
+    typename FloatOf<W>::F v[EPL];
+};
+
+template <int W, int EPL>
+__device__ __forceinline__ RowVec<W, EPL> load_row(const uint8_t* src, uint64_t rb, uint32_t row,
+                                                   uint64_t col0) {
+    using F = typename FloatOf<W>::F;
+    RowVec<W, EPL> r;
+    const F* sp = reinterpret_cast<const F*>(src + (uint64_t)row * rb) + col0;
+    if (EPL == 4) {
+        typedef F f4 __attribute__((ext_vector_type(4)));
+        const f4 v = *reinterpret_cast<const f4*>(sp);
+        r.v[0] = v.x;
+        r.v[EPL > 1 ? 1 : 0] = v.y;
+        r.v[EPL > 2 ? 2 : 0] = v.z;
+        r.v[EPL > 3 ? 3 : 0] = v.w;
+    } else {
+#pragma unroll
+        for (int q = 0; q < EPL; ++q) r.v[q] = sp[q];
+    }
+    return r;
+}
+
+// End of a run: an owned destination row gets (its value loaded when the run started + the
+// run's sum) stored back; a shared one gets atomic adds.
+template <int W, int EPL>
+__device__ __forceinline__ void srt_flush(uint8_t* dst, uint64_t rb, int64_t row, uint64_t col0,
+                                          bool owned, const RowVec<W, EPL>& old,
+                                          const typename FloatOf<W>::F (&acc)[EPL]) {
+    using F = typename FloatOf<W>::F;
+    F* d = reinterpret_cast<F*>(dst + (uint64_t)row * rb) + col0;
+    if (owned) {
+        if (EPL == 4) {
+            typedef F f4 __attribute__((ext_vector_type(4)));
+            f4 v;
+            v.x = old.v[0] + acc[0];
+            v.y = old.v[EPL > 1 ? 1 : 0] + acc[EPL > 1 ? 1 : 0];
+            v.z = old.v[EPL > 2 ? 2 : 0] + acc[EPL > 2 ? 2 : 0];
+            v.w = old.v[EPL > 3 ? 3 : 0] + acc[EPL > 3 ? 3 : 0];
+            *reinterpret_cast<f4*>(d) = v;
+        } else {
+#pragma unroll
+            for (int q = 0; q < EPL; ++q) d[q] = old.v[q] + acc[q];
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < EPL; ++q) unsafeAtomicAdd(d + q, acc[q]);
+    }
+}
+
+// Each wave walks RED_TILE sorted entries (their keys and positions held one per lane, read out
+// wave-uniformly) with RED_U rows in flight: the source rows of the next RED_U entries are loaded
+// together with the destination row of every run that starts among them, then the rows are
+// summed in order. A run the tile owns ends with a plain store of (destination + sum); a run
+// shared with a neighbouring tile ends with one atomic add per element.
+constexpr int RED_U = 8;
+template <bool GUARD, int W, int EPL>
+__global__ __launch_bounds__(256) void k_srt_reduce(uint8_t* dst, uint64_t rb,
+                                                    const uint8_t* __restrict__ src, uint64_t n,
+                                                    SortBufs b, uint32_t npasses, int64_t rlo) {
+    using F = typename FloatOf<W>::F;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t wave = ((uint64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * 256) >> 6;
+    const uint32_t buf = b.ctl[4 + npasses];
+    const uint32_t* __restrict__ keys = b.keys[buf];
+    const uint32_t* __restrict__ vals = b.vals[buf];
+    const uint64_t D = rb / W;
+    const int64_t base = GUARD ? rlo : -(int64_t)0x80000000ll;
+    const uint64_t ncb = (D + 64 * EPL - 1) / (64 * EPL);
+    for (uint64_t e0 = wave * RED_TILE; e0 < n; e0 += nwaves * RED_TILE) {
+        const uint64_t e1 = e0 + RED_TILE < n ? e0 + RED_TILE : n;
+        const uint32_t k0 = keys[e0];
+        if (k0 == SRT_SENT) continue;
+        // does the tile's first run continue a run of the previous tile, its last run the next?
+        const bool head_shared = e0 > 0 && keys[e0 - 1] == k0;
+        const uint32_t klast = keys[e1 - 1];
+        const bool tail_shared = e1 < n && klast != SRT_SENT && keys[e1] == klast;
+        // the tile's keys and positions, one per lane per group of 64 (sentinel past the tile)
+        uint32_t tk[RED_TILE / 64], tv[RED_TILE / 64];
+#pragma unroll
+        for (int j = 0; j < RED_TILE / 64; ++j) {
+            const uint64_t e = e0 + (uint64_t)j * 64 + lane;
+            tk[j] = e < e1 ? keys[e] : SRT_SENT;
+            tv[j] = e < e1 ? vals[e] : 0u;
+        }
+        for (uint64_t cb = 0; cb < ncb; ++cb) {
+            const uint64_t col0 = cb * 64 * EPL + (uint64_t)lane * EPL;
+            const bool on = col0 < D;
+            F acc[EPL];
+#pragma unroll
+            for (int q = 0; q < EPL; ++q) acc[q] = (F)-0.0;
+            uint32_t cur = k0;
+            bool first = true, stop = false;
+            RowVec<W, EPL> dcur;
+            if (on && !head_shared)
+                dcur = load_row<W, EPL>(dst + (uint64_t)(base + (int64_t)k0) * rb, rb, 0, col0);
+#pragma unroll
+            for (int j = 0; j < RED_TILE / 64; ++j) {
+                for (uint32_t l = 0; l < 64 && !stop; l += RED_U) {
+                    uint32_t kk[RED_U], vv[RED_U];
+                    RowVec<W, EPL> rv[RED_U], dv[RED_U];
+#pragma unroll
+                    for (int u = 0; u < RED_U; ++u) {
+                        kk[u] = (uint32_t)__builtin_amdgcn_readlane((int)tk[j], (int)(l + u));
+                        vv[u] = (uint32_t)__builtin_amdgcn_readlane((int)tv[j], (int)(l + u));
+                    }
+#pragma unroll
+                    for (int u = 0; u < RED_U; ++u) {
+                        if (kk[u] != SRT_SENT && on) {
+                            rv[u] = load_row<W, EPL>(src, rb, vv[u], col0);
+                            const uint32_t prev = u == 0 ? cur : kk[u - 1];
+                            if (kk[u] != prev)
+                                dv[u] = load_row<W, EPL>(dst + (uint64_t)(base + (int64_t)kk[u]) * rb,
+                                                         rb, 0, col0);
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < RED_U; ++u) {
+                        if (kk[u] == SRT_SENT) {
+                            stop = true;
+                            break;
+                        }
+                        if (kk[u] != cur) {
+                            if (on) srt_flush<W, EPL>(dst, rb, base + (int64_t)cur, col0,
+                                                      !(first && head_shared), dcur, acc);
+#pragma unroll
+                            for (int q = 0; q < EPL; ++q) acc[q] = (F)-0.0;
+                            cur = kk[u];
+                            dcur = dv[u];
+                            first = false;
+                        }
+                        if (on) {
+#pragma unroll
+                            for (int q = 0; q < EPL; ++q) acc[q] += rv[u].v[q];
+                        }
+                    }
+                }
+            }
+            // the last run of the tile: shared with the next tile only if it reaches the tile end
+            const bool last_shared = tail_shared && cur == klast;
+            if (on) srt_flush<W, EPL>(dst, rb, base + (int64_t)cur, col0,
+                                      !((first && head_shared) || last_shared), dcur, acc);
+        }
+    }
+}
+
+// Rows that failed the fast test: every element checked exactly, atomics for the allowed ones.
+template <int W>
+__global__ __launch_bounds__(256) void k_srt_slow(DevTable t, DevLog* log, uint8_t* dst, uint64_t rb,
+                                                  const int64_t* idx, const uint8_t* src,
+                                                  uint64_t n, RowsGuard rg, SortBufs b,
+                                                  unsigned long long seq, int logon) {
+    using F = typename FloatOf<W>::F;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t wave = ((uint64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * 256) >> 6;
+    const uint64_t D = rb / W;
+    const uint64_t Ki = rg.ki, Ks = rg.kc;
+    const RowGuard g = rg.g;
+    FaultAcc acc;
+    for (uint64_t r0 = wave * 64; r0 < n; r0 += nwaves * 64) {
+        uint64_t m = uniform_u64(b.slow[r0 >> 6]);
+        while (m) {
+            const uint32_t l = (uint32_t)__builtin_ctzll(m);
+            m &= m - 1;
+            const uint64_t r = r0 + l;
+            const bool iok = r < Ki;
+            if (!iok && lane == 0) acc.note((r * D) << 2);
+            const int64_t iv = iok ? idx[r] : 0;
+            uint8_t* drow = dst + (uint64_t)iv * rb;
+            for (uint64_t col = lane; col < D; col += 64) {
+                const uint64_t es = r * D + col;
+                F v = (F)0.0;
+                if (es < Ks) v = reinterpret_cast<const F*>(src)[es];
+                else acc.note((es << 2) | 1u);
+                if (elem_ok(g, iv, rb, col, W))
+                    unsafeAtomicAdd(reinterpret_cast<F*>(drow + col * W), v);
+                else
+                    acc.note((es << 2) | 2u);
+            }
+        }
+    }
+    if (logon) fold_faults(acc, log);
+}
+
+template <bool G, int W>
+static void scatter_add_sorted(const DevTable& t, DevLog* log, void* dst, uint64_t rb,
+                               const int64_t* idx, const void* src, uint64_t n,
+                               const RowsGuard& rg, uint32_t npasses, void* scratch,
+                               unsigned long long seq, int logon, const DevInfo& d,
+                               hipStream_t s) {
+    const SortBufs b = sort_bufs(scratch, n);
+    const uint32_t ntiles = (uint32_t)srt_ntiles(n);
+    const uint64_t kg = (n + SRT_BLOCK - 1) / SRT_BLOCK;
+    const uint32_t kgrid = (uint32_t)(kg < (uint64_t)d.num_cu * 8 ? kg : (uint64_t)d.num_cu * 8);
+    hipLaunchKernelGGL((k_srt_keys<G>), dim3(kgrid), dim3(SRT_BLOCK), 0, s, idx, n, rg, b);
+    for (uint32_t p = 0; p < npasses; ++p) {
+        hipLaunchKernelGGL(k_srt_hist, dim3(ntiles), dim3(SRT_BLOCK), 0, s, b, n, p);
+        hipLaunchKernelGGL(k_srt_scan, dim3(1), dim3(SCAN_BLOCK), 0, s, b, n, ntiles, p);
+        hipLaunchKernelGGL(k_srt_scatter, dim3(ntiles), dim3(SRT_BLOCK), 0, s, b, n, p);
+    }
+    const uint64_t waves = (n + RED_TILE - 1) / RED_TILE;
+    const uint64_t rg_blocks = (waves + 3) / 4;
+    const uint32_t rgrid = (uint32_t)(rg_blocks < (uint64_t)d.num_cu * 8 ? rg_blocks : (uint64_t)d.num_cu * 8);
+    const bool v4 = W == 4 && (rb / W) % 4 == 0 && (((uint64_t)src | (uint64_t)dst | rb) & 15) == 0;
+    if (v4)
+        hipLaunchKernelGGL((k_srt_reduce<G, W, 4>), dim3(rgrid), dim3(256), 0, s, (uint8_t*)dst, rb,
+                           (const uint8_t*)src, n, b, npasses, rg.g.rlo);
+    else
+        hipLaunchKernelGGL((k_srt_reduce<G, W, 1>), dim3(rgrid), dim3(256), 0, s, (uint8_t*)dst, rb,
+                           (const uint8_t*)src, n, b, npasses, rg.g.rlo);
+    if (G) {
+        const uint64_t sw = (n + 63) / 64;
+        const uint64_t sb = (sw + 3) / 4;
+        const uint32_t sgrid = (uint32_t)(sb < (uint64_t)d.num_cu * 4 ? sb : (uint64_t)d.num_cu * 4);
+        hipLaunchKernelGGL((k_srt_slow<W>), dim3(sgrid), dim3(256), 0, s, t, log, (uint8_t*)dst, rb,
+                           idx, (const uint8_t*)src, n, rg, b, seq, logon);
     }
 }
 
@@ -230,18 +646,47 @@ static void scatter_add_w(const DevTable& t, DevLog* log, void* dst, uint64_t rb
 hipError_t launch_scatter_add(bool guard, const DevTable& t, DevLog* log, const Bind* binds,
                               void* dst, uint64_t rb, const int64_t* idx, const void* src,
                               uint64_t n, uint32_t w, unsigned long long seq, int logon,
-                              const DevInfo& d, hipStream_t s) {
+                              void* scratch, const DevInfo& d, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    if (guard) {
-        const RowsGuard rg = rows_guard(binds[0], binds[1], binds[2], (uint64_t)idx, (uint64_t)src,
-                                        (uint64_t)dst, n, rb, w);
+    const RowsGuard rg = guard ? rows_guard(binds[0], binds[1], binds[2], (uint64_t)idx,
+                                            (uint64_t)src, (uint64_t)dst, n, rb, w)
+                               : rows_open(n, rb, w);
+    // sorted path: 32-bit keys (guarded: the destination's row interval minus the sentinel;
+    // unguarded: idx + 2^31), positions below 2^32
+    uint32_t npasses = 0;
+    bool sorted = scratch != nullptr && n >= SORT_MIN_N && n < (1ull << 32);
+    if (sorted && guard) {
+        if (!rg.g.bound || rg.g.rhi < rg.g.rlo) {
+            npasses = 1;  // no fast rows: every key is the sentinel, the sort is trivial
+        } else {
+            const uint64_t span = (uint64_t)rg.g.rhi - (uint64_t)rg.g.rlo;
+            if (span >= SRT_SENT) sorted = false;
+            uint32_t bits = 0;
+            while (bits < 32 && (span >> bits)) ++bits;
+            npasses = (bits + 7) / 8;
+            if (npasses == 0) npasses = 1;
+        }
+    } else if (sorted) {
+        npasses = 4;
+    }
+    if (sorted) {
+        if (guard) {
+            if (w == 4) scatter_add_sorted<true, 4>(t, log, dst, rb, idx, src, n, rg, npasses, scratch, seq, logon, d, s);
+            else scatter_add_sorted<true, 8>(t, log, dst, rb, idx, src, n, rg, npasses, scratch, seq, logon, d, s);
+        } else {
+            if (w == 4) scatter_add_sorted<false, 4>(t, log, dst, rb, idx, src, n, rg, npasses, scratch, seq, logon, d, s);
+            else scatter_add_sorted<false, 8>(t, log, dst, rb, idx, src, n, rg, npasses, scratch, seq, logon, d, s);
+        }
+    } else if (guard) {
         if (w == 4) scatter_add_w<true, 4>(t, log, dst, rb, idx, src, n, rg, seq, logon, d, s);
         else scatter_add_w<true, 8>(t, log, dst, rb, idx, src, n, rg, seq, logon, d, s);
     } else {
-        const RowsGuard rg = rows_open(n, rb, w);
         if (w == 4) scatter_add_w<false, 4>(t, log, dst, rb, idx, src, n, rg, seq, logon, d, s);
         else scatter_add_w<false, 8>(t, log, dst, rb, idx, src, n, rg, seq, logon, d, s);
     }
+    if (guard && logon)
+        return launch_fault_finish(t, log, rows_fault_site(5 /*OP_SCATTER_ADD*/, w, 2, rb, rg.ki, idx,
+                                                             src, dst), seq, s);
     return hipGetLastError();
 }
 

@@ -36,17 +36,32 @@ hipError_t launch_gather(bool guard, const DevTable& t, DevLog* log, const Bind*
                          uint32_t w, unsigned long long seq, int logon, const DevInfo& d,
                          hipStream_t s);
 
+// Scatter with accumulate = 1 uses `scratch` (device memory of at least
+// scatter_add_scratch_bytes(n) bytes, or null for the chunk path) for its sort; calls that share
+// a scratch buffer must be ordered on one stream.
 hipError_t launch_scatter(bool guard, const DevTable& t, DevLog* log, const Bind* binds, void* dst,
                           uint64_t row_bytes, const int64_t* idx, const void* src, uint64_t n,
                           uint32_t w, int accumulate, unsigned long long seq, int logon,
-                          const DevInfo& d, hipStream_t s);
+                          void* scratch, const DevInfo& d, hipStream_t s);
 
 hipError_t launch_scatter_add(bool guard, const DevTable& t, DevLog* log, const Bind* binds,
                               void* dst, uint64_t rb, const int64_t* idx, const void* src,
                               uint64_t n, uint32_t w, unsigned long long seq, int logon,
-                              const DevInfo& d, hipStream_t s);
+                              void* scratch, const DevInfo& d, hipStream_t s);
+
+size_t scatter_add_scratch_bytes(uint64_t n);
+
+// Scatter-add calls of at least this many rows sort their destination keys (when given scratch).
+constexpr uint64_t SORT_MIN_N = 1u << 15;
 
 hipError_t launch_log_reset(DevLog* log, hipStream_t s);
+
+// After a guarded row kernel: folds the launch's denial count into the log and records the
+// smallest key if the log is empty.
+hipError_t launch_fault_finish(const DevTable& t, DevLog* log, const FaultSite& f,
+                               unsigned long long seq, hipStream_t s);
+FaultSite rows_fault_site(uint32_t op, uint32_t w, uint32_t row_operand, uint64_t rb, uint64_t ki,
+                          const void* idx, const void* cont, const void* rowp);
 
 // ---- batched multi-client launch (device images of the public request/result layouts) ----
 struct BatchReq {

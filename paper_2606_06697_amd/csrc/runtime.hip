@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <unordered_map>
 #include <vector>
@@ -71,6 +72,9 @@ struct agile_rt {
     hipEvent_t upload_done = nullptr;
     bool upload_pending = false;
     std::vector<hipStream_t> streams_used;
+    // sort scratch of the scatter-add (grown on demand)
+    void* sa_scratch = nullptr;
+    size_t sa_bytes = 0;
 };
 
 // Image layout: split64 | split32 | (64-byte aligned) rec | radix
@@ -390,6 +394,7 @@ int agile_rt_destroy(agile_rt* rt) {
     if (rt->hstage) (void)hipHostFree(rt->hstage);
     if (rt->hlog) (void)hipHostFree(rt->hlog);
     if (rt->dmem) (void)hipFree(rt->dmem);
+    if (rt->sa_scratch) (void)hipFree(rt->sa_scratch);
     delete rt;
     return rc;
 }
@@ -500,6 +505,26 @@ static bool policy_ok(int policy) {
     return policy == AGILE_POLICY_SUPPRESS_LOG || policy == AGILE_POLICY_SUPPRESS_ONLY;
 }
 
+// Scratch of the sorted scatter-add, grown on demand; the old buffer is released only after the
+// device has finished every launch that may still use it. Returns null when it cannot grow (the
+// caller then takes the chunk path, which needs no scratch).
+static void* grow_scratch(void*& buf, size_t& cap, size_t need) {
+    if (need <= cap) return buf;
+    if (buf) {
+        if (hipDeviceSynchronize() != hipSuccess) return nullptr;
+        (void)hipFree(buf);
+        buf = nullptr;
+        cap = 0;
+    }
+    const size_t want = need + need / 4;
+    if (hipMalloc(&buf, want) != hipSuccess) {
+        buf = nullptr;
+        return nullptr;
+    }
+    cap = want;
+    return buf;
+}
+
 // Binding of a pointer argument of a guarded call: the USER range containing p, from the host
 // copy of the table (the state the launch is ordered after), or the empty interval.
 static Bind host_bind(const agile_rt* rt, uint64_t p) {
@@ -595,8 +620,11 @@ int agile_guarded_scatter(agile_rt* rt, void* d_dst, uint64_t row_bytes, const i
     const unsigned long long seq = rt->seq++;
     const Bind b[3] = {host_bind(rt, (uint64_t)d_idx), host_bind(rt, (uint64_t)d_src),
                        host_bind(rt, (uint64_t)d_dst)};
+    void* scr = (accumulate && n >= SORT_MIN_N)
+                    ? grow_scratch(rt->sa_scratch, rt->sa_bytes, scatter_add_scratch_bytes(n))
+                    : nullptr;
     if (launch_scatter(true, rt->tab, rt->d_log, b, d_dst, row_bytes, d_idx, d_src, n, w, accumulate,
-                       seq, policy == AGILE_POLICY_SUPPRESS_LOG, rt->info, s) != hipSuccess)
+                       seq, policy == AGILE_POLICY_SUPPRESS_LOG, scr, rt->info, s) != hipSuccess)
         return AGILE_EDEVICE;
     return AGILE_OK;
 }
@@ -826,8 +854,20 @@ int agile_unguarded_scatter(void* d_dst, uint64_t row_bytes, const int64_t* d_id
     int rc = rows_args_ok(row_bytes, n, dtype, d_dst, d_src, &w);
     if (rc != AGILE_OK) return rc;
     if (n && (!d_dst || !d_src || !d_idx)) return AGILE_EINVAL;
+    void* scr = nullptr;
+    if (accumulate && n >= SORT_MIN_N) {
+        // one scratch buffer per device for the unguarded twin (its calls on a device are
+        // ordered by the caller)
+        static std::mutex mu;
+        static std::vector<std::pair<void*, size_t>> per_dev;
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        std::lock_guard<std::mutex> lk(mu);
+        if ((size_t)dev >= per_dev.size()) per_dev.resize(dev + 1, {nullptr, 0});
+        scr = grow_scratch(per_dev[dev].first, per_dev[dev].second, scatter_add_scratch_bytes(n));
+    }
     return launch_scatter(false, DevTable{}, nullptr, nullptr, d_dst, row_bytes, d_idx, d_src, n, w,
-                          accumulate, 0, 0, current_info(),
+                          accumulate, 0, 0, scr, current_info(),
                           static_cast<hipStream_t>(stream)) == hipSuccess
                ? AGILE_OK
                : AGILE_EDEVICE;

@@ -1,0 +1,129 @@
+"""Guarded scatter-add on the sorted path (calls of at least 32,768 rows) against the oracle.
+
+One device arena holds the destination table (USER), a protected canary right after it, an
+unregistered hole, another USER allocation, the index buffer and the source rows. Source and
+destination values are small integers, so every sum is exact in any order and the arena must
+equal the oracle's memory byte for byte. Cases: hot and hostile indices (protected, hole,
+other allocation, negative, huge), an index buffer and a source buffer that run out before n, an
+interior destination pointer (negative indices allowed), a destination with no binding (no row
+takes the sorted path), and the unguarded twin on valid indices.
+"""
+import random
+
+import numpy as np
+import pytest
+
+from gpu_util import Arena, Twin, log_matches, need_gpu
+from oracle import guarded as G
+
+pytestmark = pytest.mark.gpu
+
+DST_ROWS = 3000
+NMAX = 70001
+CASES = [(4, 1), (4, 3), (4, 64), (4, 128), (8, 2), (8, 32)]
+
+
+def layout(w, D):
+    rb = w * D
+    off = {}
+    o = 0
+    for name, size in (("dst", DST_ROWS * rb), ("prot", 4096), ("hole", 4096), ("other", 8192),
+                       ("idx", NMAX * 8), ("src", NMAX * rb)):
+        o = (o + 255) // 256 * 256
+        off[name] = (o, o + size)
+        o += size
+    return off, (o + 4095) // 4096 * 4096
+
+
+def setup(w, D, seed):
+    need_gpu()
+    off, size = layout(w, D)
+    ar = Arena(size, seed)
+    tw = Twin(16)
+    kinds = {"dst": 0, "prot": 1, "other": 0, "idx": 0, "src": 0}
+    for k, kind in kinds.items():
+        lo, hi = off[k]
+        tw.insert(ar.addr(lo), hi - lo, kind)
+    dt = np.float32 if w == 4 else np.float64
+    rng = np.random.default_rng(seed)
+    for k in ("dst", "src", "other"):
+        lo, hi = off[k]
+        ar.write(lo, rng.integers(-50, 51, (hi - lo) // w).astype(dt))
+    return ar, tw, off
+
+
+def indices(rng, n, rows, extra, neg_ok=0):
+    """Hot rows (Zipf-like), uniform rows and hostile values, shuffled."""
+    hot = [rng.randrange(rows) for _ in range(5)]
+    bad = [rows, rows + 1, -1 - neg_ok, 3 * rows, -(1 << 62), (1 << 62), -(1 << 63),
+           (1 << 63) - 1, (1 << 40) + 3] + list(extra)
+    vals = []
+    for _ in range(n):
+        u = rng.random()
+        if u < 0.5:
+            vals.append(hot[min(int(rng.expovariate(1.0)), 4)])
+        elif u < 0.9:
+            vals.append(rng.randrange(-neg_ok, rows))
+        else:
+            vals.append(rng.choice(bad))
+    return np.array(vals, dtype=np.int64)
+
+
+@pytest.mark.parametrize("w,D", CASES)
+def test_sorted_scatter_add_against_oracle(w, D):
+    ar, tw, off = setup(w, D, 40 + D + w)
+    rb = w * D
+    dtype = 0 if w == 4 else 1
+    ol = G.FaultLog()
+    rng = random.Random(1000 + D * 10 + w)
+    base = ar.addr(off["dst"][0])
+    hostile_rows = [(ar.addr(off["prot"][0]) - base) // rb + 1,
+                    (ar.addr(off["hole"][0]) - base) // rb + 1,
+                    (ar.addr(off["other"][0]) - base) // rb + 2]
+    trials = [
+        dict(dst=base, n=40000, idx_end=False, src_end=False, neg=0),
+        dict(dst=base, n=NMAX, idx_end=True, src_end=True, neg=0),
+        dict(dst=base + 100 * rb + w, n=32768, idx_end=False, src_end=False, neg=100),
+        dict(dst=ar.addr(off["hole"][0]), n=33000, idx_end=False, src_end=False, neg=0),
+    ]
+    for t, tr in enumerate(trials):
+        n = tr["n"]
+        rows = DST_ROWS - 101 if tr["neg"] else DST_ROWS
+        idx = indices(rng, n, rows, hostile_rows, tr["neg"])
+        ilo, ihi = off["idx"]
+        idx_ptr = ar.addr(ihi - 8 * (n - 700)) if tr["idx_end"] else ar.addr(ilo)
+        ar.write(idx_ptr - ar.base, idx[:(ihi - (idx_ptr - ar.base)) // 8])
+        slo, shi = off["src"]
+        src = ar.addr(shi - rb * (n - 1234) - w) if tr["src_end"] else ar.addr(slo)
+        tw.g.agile_guarded_scatter(tw.h, tr["dst"], rb, idx_ptr, src, n, dtype, 1)
+        G.scatter_vec(tw.ot, ar.mem, ol, tw.next_seq(), tr["dst"], rb, idx_ptr, src, n, w, True)
+        ar.check(f"scatter-add w={w} D={D} trial {t} n={n}")
+        log_matches(tw, ol, f"scatter-add w={w} D={D} trial {t}")
+    tw.close()
+
+
+@pytest.mark.parametrize("w,D", [(4, 64), (8, 2)])
+def test_unguarded_sorted_scatter_add_matches_guarded(w, D):
+    ar, tw, off = setup(w, D, 77 + D)
+    rb = w * D
+    dtype = 0 if w == 4 else 1
+    rng = random.Random(5 + D)
+    n = 50001
+    idx = indices(rng, n, DST_ROWS, [], 0)
+    idx[(idx < 0) | (idx >= DST_ROWS)] = 7                  # valid rows only
+    ar.write(off["idx"][0], idx)
+    base = ar.addr(off["dst"][0])
+    before = ar.dev.clone()
+    tw.g.agile_guarded_scatter(tw.h, base, rb, ar.addr(off["idx"][0]), ar.addr(off["src"][0]), n,
+                               dtype, 1)
+    guarded = ar.dev.clone()
+    ar.dev.copy_(before)
+    tw.g.agile_unguarded_scatter(base, rb, ar.addr(off["idx"][0]), ar.addr(off["src"][0]), n,
+                                 dtype, 1)
+    assert bool((ar.dev == guarded).all())
+    G.scatter_vec(tw.ot, ar.mem, G.FaultLog(), 0, base, rb, ar.addr(off["idx"][0]),
+                  ar.addr(off["src"][0]), n, w, True)
+    ar.check("unguarded sorted scatter-add")
+    rc, f = tw.rt.fault_log(clear=True)
+    assert f["count"] == 0
+    tw.close()
