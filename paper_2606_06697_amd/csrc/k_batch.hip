@@ -15,28 +15,14 @@ namespace agile {
 constexpr int BBLOCK = 256;
 constexpr uint64_t TILE_PTRS = 2048;       // pointers per validation tile (8 per thread)
 constexpr uint64_t TILE_COPY = 1ull << 20; // bytes per copy tile
+constexpr int COPY_U = 16;                 // 16-byte vectors in flight per thread
+constexpr uint64_t COPY_CHUNK = (uint64_t)BBLOCK * COPY_U * 16;  // one pass of a workgroup
 constexpr uint64_t TILE_ROWS = 16384;      // rows per gather tile
 constexpr int VQ = 8;
 
 __device__ inline void tiles_of(const BatchReq& q, uint64_t& vt, uint64_t& ct) {
     vt = (q.nptr + TILE_PTRS - 1) / TILE_PTRS;
     ct = (q.copy_bytes + TILE_COPY - 1) / TILE_COPY;
-}
-
-// Binding of one pointer by one lane (the finishing workgroup's bookkeeping).
-__device__ inline Bind bind_lane(const DevTable& t, uint64_t p) {
-    Bind r{0, 0};
-    const int64_t b = bucket_search_lane(t, p);
-    if (b < 0) return r;
-    const PairRec rec = load_rec(t.rec + b);
-    const bool second = rec.base1 <= p;
-    const uint64_t end = second ? rec.end1 : rec.end0;
-    const uint32_t meta = second ? rec.meta1 : rec.meta0;
-    if (p < end && (meta & 3u) == KIND_USER) {
-        r.lo = second ? rec.base1 : t.split64[b];
-        r.hi = end;
-    }
-    return r;
 }
 
 // VQ pointer queries per lane, searched together (uniform trip count over the client table).
@@ -81,8 +67,28 @@ __device__ inline void copy_tile(uint8_t* dst, const uint8_t* src, uint64_t o0, 
     const uint64_t K = Ks < Kd ? Ks : Kd;
     const bool vec = (((uint64_t)dst | (uint64_t)src | o0) & 15) == 0;
     uint64_t done = o0;
-    if (vec) {
-        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    if (vec && o1 <= K) {
+        // the whole range lies inside both allowed prefixes: CU vectors in flight per thread
+        constexpr int CU = COPY_U;
+        const u32x4* sv = reinterpret_cast<const u32x4*>(src);
+        u32x4* dv = reinterpret_cast<u32x4*>(dst);
+        const uint64_t v0 = o0 / 16, v1 = o1 / 16;
+        for (uint64_t v = v0 + threadIdx.x; v < v1; v += (uint64_t)BBLOCK * CU) {
+            u32x4 x[CU];
+#pragma unroll
+            for (int u = 0; u < CU; ++u) {
+                const uint64_t w = v + (uint64_t)u * BBLOCK;
+                if (w < v1) x[u] = __builtin_nontemporal_load(sv + w);
+            }
+#pragma unroll
+            for (int u = 0; u < CU; ++u) {
+                const uint64_t w = v + (uint64_t)u * BBLOCK;
+                if (w < v1) __builtin_nontemporal_store(x[u], dv + w);
+            }
+        }
+        done = v1 * 16;
+    } else if (vec) {
         const uint64_t v0 = o0 / 16, v1 = o1 / 16;
         for (uint64_t v = v0 + threadIdx.x; v < v1; v += BBLOCK) {
             const uint64_t b0 = v * 16;
@@ -105,18 +111,14 @@ __device__ inline void copy_tile(uint8_t* dst, const uint8_t* src, uint64_t o0, 
     }
 }
 
-__device__ inline void gather_tile(const DevTable& t, const BatchReq& q, uint64_t i0, uint64_t i1,
+__device__ inline void gather_tile(const BatchReq& q, const RowsGuard& rg, uint64_t i0, uint64_t i1,
                                    FaultAcc& acc) {
-    const uint64_t rb = q.gather_row_bytes, D = rb / 4, n = q.gather_n;
+    const uint64_t rb = q.gather_row_bytes, D = rb / 4;
     const int64_t* idx = reinterpret_cast<const int64_t*>(q.gather_idx);
     const uint8_t* T = reinterpret_cast<const uint8_t*>(q.gather_table);
     uint8_t* out = reinterpret_cast<uint8_t*>(q.gather_out);
-    const Bind bi = bind_wave(t, q.gather_idx);
-    const Bind bt = bind_wave(t, q.gather_table);
-    const Bind bo = bind_wave(t, q.gather_out);
-    const uint64_t Ki = clip_prefix(bi, q.gather_idx, n, 8);
-    const uint64_t Ko = clip_prefix(bo, q.gather_out, n * D, 4);
-    const RowGuard g = row_guard(bt, q.gather_table, rb);
+    const uint64_t Ki = rg.ki, Ko = rg.kc;
+    const RowGuard g = rg.g;
     for (uint64_t i = i0 + threadIdx.x; i < i1; i += BBLOCK) {
         const bool iok = i < Ki;
         const int64_t iv = iok ? idx[i] : 0;
@@ -155,8 +157,7 @@ __device__ inline void finish_request(const BatchArgs& A, uint32_t r) {
     f.first_owner = -1;
     if (q.copy_bytes) {
         const uint64_t n = q.copy_bytes;
-        const uint64_t Ks = clip_prefix(bind_lane(t, q.copy_src), q.copy_src, n, 1);
-        const uint64_t Kd = clip_prefix(bind_lane(t, q.copy_dst), q.copy_dst, n, 1);
+        const uint64_t Ks = A.guards[r].copy_ks, Kd = A.guards[r].copy_kd;
         const uint64_t cnt = (n - Ks) + (n - Kd);
         if (cnt) {
             f.count += cnt;
@@ -191,7 +192,7 @@ __device__ inline void finish_request(const BatchArgs& A, uint32_t r) {
                 Aa = (__int128)q.gather_idx + (__int128)(8 * i);
                 w = 8;
             } else if (operand == 1) {
-                const uint64_t Ki = clip_prefix(bind_lane(t, q.gather_idx), q.gather_idx, q.gather_n, 8);
+                const uint64_t Ki = A.guards[r].gather.ki;
                 const int64_t v = i < Ki ? reinterpret_cast<const int64_t*>(q.gather_idx)[i] : 0;
                 Aa = (__int128)q.gather_table + (__int128)v * (__int128)q.gather_row_bytes +
                      (__int128)(col * 4);
@@ -226,25 +227,23 @@ __device__ inline void finish_request(const BatchArgs& A, uint32_t r) {
 }
 
 __global__ __launch_bounds__(BBLOCK) void k_batch(BatchArgs A) {
-    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_tile, s_next;
     __shared__ uint32_t s_minfail;
     const uint32_t tid = threadIdx.x;
+    if (tid == 0) s_next = atomicAdd(&A.ctl->next, 1u);
     while (true) {
+        __syncthreads();
         if (tid == 0) {
-            s_tile = atomicAdd(&A.ctl->next, 1u);
+            s_tile = s_next;
             s_minfail = 0xFFFFFFFFu;
         }
         __syncthreads();
         const uint64_t tile = s_tile;
         if (tile >= A.ntiles) break;  // uniform: every wave of the block leaves together
-        // request owning this tile: last r with tstart[r] <= tile
-        uint32_t lo = 0, len = A.nreq;
-        while (len > 1) {
-            const uint32_t half = len >> 1;
-            lo = A.tstart[lo + half] <= tile ? lo + half : lo;
-            len -= half;
-        }
-        const uint32_t r = lo;
+        // claim the next tile now, so the counter's latency overlaps this tile's work (a
+        // claimed tile is always processed: the loop only ends on an index past the last tile)
+        if (tid == 0) s_next = atomicAdd(&A.ctl->next, 1u);
+        const uint32_t r = A.tile_req[tile];
         const BatchReq q = A.reqs[r];
         const DevTable& t = A.tables[q.client];
         uint64_t vt, ct;
@@ -259,19 +258,20 @@ __global__ __launch_bounds__(BBLOCK) void k_batch(BatchArgs A) {
             __syncthreads();
             if (tid == 0 && s_minfail != 0xFFFFFFFFu) atomicMin(&A.scratch[r].minfail, s_minfail);
         } else if (local < vt + ct) {
-            const uint64_t o0 = (local - vt) * TILE_COPY;
-            const uint64_t o1 = o0 + TILE_COPY < q.copy_bytes ? o0 + TILE_COPY : q.copy_bytes;
-            const Bind bs = bind_wave(t, q.copy_src);
-            const Bind bd = bind_wave(t, q.copy_dst);
-            const uint64_t Ks = clip_prefix(bs, q.copy_src, q.copy_bytes, 1);
-            const uint64_t Kd = clip_prefix(bd, q.copy_dst, q.copy_bytes, 1);
-            copy_tile(reinterpret_cast<uint8_t*>(q.copy_dst), reinterpret_cast<const uint8_t*>(q.copy_src),
-                      o0, o1, Ks, Kd);
+            // copy tile j of ct takes chunks j, j + ct, j + 2 ct, ... of COPY_CHUNK bytes, so the
+            // workgroups working on one request at the same time read one contiguous window
+            const uint64_t j = local - vt;
+            for (uint64_t o0 = j * COPY_CHUNK; o0 < q.copy_bytes; o0 += ct * COPY_CHUNK) {
+                const uint64_t o1 = o0 + COPY_CHUNK < q.copy_bytes ? o0 + COPY_CHUNK : q.copy_bytes;
+                copy_tile(reinterpret_cast<uint8_t*>(q.copy_dst),
+                          reinterpret_cast<const uint8_t*>(q.copy_src), o0, o1,
+                          A.guards[r].copy_ks, A.guards[r].copy_kd);
+            }
         } else if (q.gather_n) {
             const uint64_t i0 = (local - vt - ct) * TILE_ROWS;
             const uint64_t i1 = i0 + TILE_ROWS < q.gather_n ? i0 + TILE_ROWS : q.gather_n;
             FaultAcc acc;
-            gather_tile(t, q, i0, i1, acc);
+            gather_tile(q, A.guards[r].gather, i0, i1, acc);
             const unsigned long long c = wave_sum_u64(acc.cnt);
             const unsigned long long m = wave_min_u64(acc.mk);
             if ((tid & 63u) == 0 && c) {
@@ -287,13 +287,12 @@ __global__ __launch_bounds__(BBLOCK) void k_batch(BatchArgs A) {
                 finish_request(A, r);
             }
         }
-        __syncthreads();
     }
 }
 
 hipError_t launch_batch(const BatchArgs& A, const DevInfo& d, hipStream_t s) {
     if (A.ntiles == 0) return hipSuccess;
-    uint64_t grid = (uint64_t)d.num_cu * 4;
+    uint64_t grid = (uint64_t)d.num_cu * 2;
     if (grid > A.ntiles) grid = A.ntiles;
     hipLaunchKernelGGL(k_batch, dim3((uint32_t)grid), dim3(BBLOCK), 0, s, A);
     return hipGetLastError();

@@ -100,9 +100,18 @@ struct agile_req_result_dev {
 };
 static_assert(sizeof(agile_req_result_dev) == 72, "mirrors agile_req_result");
 
+// Guard of one request, computed on the host from its client's table at launch time (the
+// bindings of its copy and gather arguments as allowed prefixes and a row interval).
+struct BatchGuard {
+    uint64_t copy_ks, copy_kd;  // allowed byte prefixes of copy_src and copy_dst
+    RowsGuard gather;           // gather: index / out prefixes and the table's row interval
+};
+
 struct BatchArgs {
     BatchCtl* ctl;
     const uint64_t* tstart;  // nreq + 1 entries: first tile of each request, then the total
+    const uint32_t* tile_req;  // ntiles entries: the request each tile belongs to
+    const BatchGuard* guards;  // nreq entries
     const BatchReq* reqs;
     BatchScratch* scratch;
     const DevTable* tables;

@@ -729,12 +729,15 @@ int agile_batch_run(agile_clients* cs, const agile_request* reqs, uint32_t nreq,
         const int rc = prepare(rt, s);
         if (rc != AGILE_OK) return rc;
     }
-    // layout: ctl | tstart[nreq+1] | reqs | scratch | tables
+    // layout: ctl | tstart[nreq+1] | reqs | scratch | tables | guards[nreq] | tile_req[ntiles]
+    if (ntiles > 0xFFFFFFFFull) return AGILE_EINVAL;
     const size_t o_ts = align64(sizeof(BatchCtl));
     const size_t o_rq = o_ts + align64((size_t)(nreq + 1) * 8);
     const size_t o_sc = o_rq + align64((size_t)nreq * sizeof(BatchReq));
     const size_t o_tb = o_sc + align64((size_t)nreq * sizeof(BatchScratch));
-    const size_t bytes = o_tb + align64((size_t)ncl * sizeof(DevTable));
+    const size_t o_gd = o_tb + align64((size_t)ncl * sizeof(DevTable));
+    const size_t o_tr = o_gd + align64((size_t)nreq * sizeof(BatchGuard));
+    const size_t bytes = o_tr + align64((size_t)ntiles * 4);
     BatchSlot& sl = cs->slot[cs->next];
     cs->next = (cs->next + 1) % BATCH_SLOTS;
     if (sl.used) {
@@ -761,12 +764,25 @@ int agile_batch_run(agile_clients* cs, const agile_request* reqs, uint32_t nreq,
     BatchReq* rq = reinterpret_cast<BatchReq*>(h + o_rq);
     BatchScratch* sc = reinterpret_cast<BatchScratch*>(h + o_sc);
     DevTable* tb = reinterpret_cast<DevTable*>(h + o_tb);
+    BatchGuard* gd = reinterpret_cast<BatchGuard*>(h + o_gd);
+    uint32_t* tr = reinterpret_cast<uint32_t*>(h + o_tr);
     uint64_t acc = 0;
     for (uint32_t r = 0; r < nreq; ++r) {
         std::memcpy(&rq[r], &reqs[r], sizeof(BatchReq));
         const uint64_t k = batch_tiles(rq[r]);
+        for (uint64_t j = 0; j < k; ++j) tr[acc + j] = r;
         ts[r] = acc;
         acc += k;
+        // the request's arguments bound against its own client's table (host lookup)
+        const agile_rt* crt = cs->tables[rq[r].client];
+        const BatchReq& q = rq[r];
+        gd[r].copy_ks = clip_prefix(host_bind(crt, q.copy_src), q.copy_src, q.copy_bytes, 1);
+        gd[r].copy_kd = clip_prefix(host_bind(crt, q.copy_dst), q.copy_dst, q.copy_bytes, 1);
+        gd[r].gather = q.gather_n
+                           ? rows_guard(host_bind(crt, q.gather_idx), host_bind(crt, q.gather_out),
+                                        host_bind(crt, q.gather_table), q.gather_idx, q.gather_out,
+                                        q.gather_table, q.gather_n, q.gather_row_bytes, 4)
+                           : rows_open(0, 4, 4);
         sc[r].minfail = 0xFFFFFFFFu;
         sc[r].remaining = (unsigned int)k;
         sc[r].gcount = 0;
@@ -784,6 +800,8 @@ int agile_batch_run(agile_clients* cs, const agile_request* reqs, uint32_t nreq,
     A.reqs = reinterpret_cast<const BatchReq*>(d + o_rq);
     A.scratch = reinterpret_cast<BatchScratch*>(d + o_sc);
     A.tables = reinterpret_cast<const DevTable*>(d + o_tb);
+    A.guards = reinterpret_cast<const BatchGuard*>(d + o_gd);
+    A.tile_req = reinterpret_cast<const uint32_t*>(d + o_tr);
     A.ptrs = reinterpret_cast<const ulonglong2*>(d_ptrs);
     A.pv = d_ptr_verdict;
     A.po = d_ptr_owner;
