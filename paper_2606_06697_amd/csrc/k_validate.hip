@@ -153,6 +153,8 @@ __device__ __forceinline__ void chunk_wide(const DevTable& t, const unsigned cha
 }
 
 // ---------------------------------------------------------------- packed 16-byte records
+// Offsets inside a bucket (the second range's base, both ends) are below 2^32 whenever packed
+// records are built, so after one 64-bit subtraction the classification runs on 32-bit values.
 template <bool COMP, int LEVELS, int QPT, bool TAIL>
 __device__ __forceinline__ void chunk_packed(const DevTable& t, const unsigned char* lds_raw,
                                              const uint32_t* ri, const ulonglong2 (&x)[QPT],
@@ -160,12 +162,12 @@ __device__ __forceinline__ void chunk_packed(const DevTable& t, const unsigned c
                                              int32_t* __restrict__ owner, uint64_t c0,
                                              uint32_t lane) {
     using K = typename KeyT<COMP>::T;
-    const K* top = reinterpret_cast<const K*>(lds_raw);
     const uint32_t ntop = t.ntop;
     K key[QPT];
     uint32_t p[QPT];
     keys_and_starts<COMP, QPT>(t, ri, x, key, p);
     // unrolled lifting: every step is a constant, so the LDS reads use immediate offsets
+    const K* top = reinterpret_cast<const K*>(lds_raw);
 #pragma unroll
     for (int lv = LEVELS - 1; lv >= 0; --lv) {
         const uint32_t step = 1u << lv;
@@ -189,20 +191,24 @@ __device__ __forceinline__ void chunk_packed(const DevTable& t, const unsigned c
 #pragma unroll
     for (int j = 0; j < QPT; ++j) r[j] = t.nrec[b[j]];
     const uint32_t m1 = t.w1 >= 32 ? 0xFFFFFFFFu : (1u << t.w1) - 1u;
+    const uint32_t sb = t.sb, w1 = t.w1;
     uint8_t* vp = verdict + c0 + lane;
     int32_t* op = owner + c0 + lane;
 #pragma unroll
     for (int j = 0; j < QPT; ++j) {
-        const uint64_t base0 = COMP ? t.gmin + ((uint64_t)sp[j] << t.shift) : (uint64_t)sp[j];
-        const uint64_t rel = x[j].x - base0;
-        const uint64_t ob1 = (uint64_t)(r[j].x & m1) << t.sb;
-        const uint32_t oe0 = t.w1 >= 32 ? 0u : r[j].x >> t.w1;
+        // offset from the bucket base; an address 2^32 or more past it is in no range of it
+        const uint64_t rel64 = COMP ? (x[j].x - t.gmin) - ((uint64_t)sp[j] << t.shift)
+                                    : x[j].x - (uint64_t)sp[j];
+        const bool near = (uint32_t)(rel64 >> 32) == 0u;
+        const uint32_t rel = (uint32_t)rel64;
+        const uint32_t ob1 = (r[j].x & m1) << sb;
+        const uint32_t oe0 = w1 >= 32 ? 0u : r[j].x >> w1;
         const bool second = rel >= ob1;
         const uint32_t oend = second ? r[j].y : oe0;
         const uint32_t meta = second ? r[j].w : r[j].z;
-        const bool inside = found[j] && rel < (uint64_t)oend;
+        const bool inside = found[j] && near && rel < oend;
         // inside a range, oend - rel >= 1, so max(len, 1) <= oend - rel iff len <= oend - rel
-        const bool fits = x[j].y <= (uint64_t)(oend - (uint32_t)rel);
+        const bool fits = (uint32_t)(x[j].y >> 32) == 0u && (uint32_t)x[j].y <= oend - rel;
         const uint8_t v = !inside ? V_UNMAPPED
                                   : ((meta & 3u) != KIND_USER ? V_PROTECTED
                                                               : (fits ? V_ALLOW : V_STRADDLE));

@@ -121,6 +121,7 @@ static void build_narrow(DevTable& t, const uint64_t* s64, const PairRec* rec, u
             me1 = std::max(me1, rec[b].end1 - s64[b]);
         }
     }
+    if (sb >= 32) sb = 0;  // no bucket holds a second range
     // a missing second range gets a base at or past the first end and an end of 0, so an
     // address past the first range classifies as unmapped either way
     auto ob1 = [&](uint32_t b) -> uint64_t {
@@ -131,6 +132,8 @@ static void build_narrow(DevTable& t, const uint64_t* s64, const PairRec* rec, u
     for (uint32_t b = 0; b < nb; ++b) mb1 = std::max(mb1, ob1(b));
     const uint32_t w1 = bitlen(mb1), w2 = bitlen(me0), w3 = bitlen(me1);
     if (w1 + w2 > 32 || w3 > 32) return;
+    // the kernel rebuilds the second base as a 32-bit value (field << sb)
+    if (sb >= 32 || (mb1 << sb) > 0xFFFFFFFFull) return;
     for (uint32_t b = 0; b < nb; ++b) {
         const bool two = rec[b].base1 != U64MAX;
         nrec[4 * b + 0] = (uint32_t)(ob1(b) | ((rec[b].end0 - s64[b]) << w1));
