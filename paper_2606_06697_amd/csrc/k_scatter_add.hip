@@ -5,9 +5,9 @@
 // Sorted path (large calls). Rows that pass the guard's fast test (index readable, source row
 // wholly inside its allowed prefix, destination row inside the binding's row interval) get a
 // 32-bit key, their destination row's offset inside that interval; every other row gets the
-// largest key. A stable LSD radix sort (8-bit digits; per pass: per-tile digit histograms, one
-// workgroup's exclusive scan, a stable scatter ranked with wave ballots; a pass whose digit is the
-// same for every key is skipped on the device) orders (key, position) pairs by destination row,
+// largest key. A stable LSD radix sort (8-bit digits; per pass: per-tile digit histograms, their
+// exclusive scan, a stable scatter ranked with wave ballots; a pass whose digit is the same for
+// every key is skipped on the device) orders (key, position) pairs by destination row,
 // position ascending. Each wave then walks a tile of 256 sorted entries and sums the source rows
 // of each run of equal keys in position order; a run that lies wholly inside the tile owns its
 // destination row and adds with a plain read-modify-write, a run that crosses a tile boundary
@@ -217,6 +217,7 @@ struct SortBufs {
     uint32_t* vals[2];
     uint32_t* hist;  // [256 * ntiles], scanned in place
     uint32_t* ctl;   // [CTL_WORDS]
+    uint32_t* dstart;  // [256]: digit totals, then the first output position of each digit
     uint64_t* slow;  // [ceil(n / 64)]: bit l of word w marks row 64 w + l as failing the fast test
 };
 
@@ -224,7 +225,7 @@ static inline uint64_t srt_ntiles(uint64_t n) { return (n + SRT_TILE - 1) / SRT_
 
 size_t scatter_add_scratch_bytes(uint64_t n) {
     const uint64_t a = ((n * 4 + 255) / 256) * 256;
-    return 4 * a + srt_ntiles(n) * 256 * 4 + 256 + ((n + 63) / 64) * 8;
+    return 4 * a + srt_ntiles(n) * 256 * 4 + 256 + 1024 + ((n + 63) / 64) * 8;
 }
 
 static SortBufs sort_bufs(void* scratch, uint64_t n) {
@@ -237,7 +238,8 @@ static SortBufs sort_bufs(void* scratch, uint64_t n) {
     b.vals[1] = reinterpret_cast<uint32_t*>(p + 3 * a);
     b.hist = reinterpret_cast<uint32_t*>(p + 4 * a);
     b.ctl = reinterpret_cast<uint32_t*>(p + 4 * a + srt_ntiles(n) * 256 * 4);
-    b.slow = reinterpret_cast<uint64_t*>(p + 4 * a + srt_ntiles(n) * 256 * 4 + 256);
+    b.dstart = reinterpret_cast<uint32_t*>(p + 4 * a + srt_ntiles(n) * 256 * 4 + 256);
+    b.slow = reinterpret_cast<uint64_t*>(p + 4 * a + srt_ntiles(n) * 256 * 4 + 256 + 1024);
     return b;
 }
 
@@ -289,65 +291,55 @@ __global__ __launch_bounds__(SRT_BLOCK) void k_srt_hist(SortBufs b, uint64_t n, 
     b.hist[(uint64_t)tid * gridDim.x + blockIdx.x] = h[tid];
 }
 
-// One workgroup: exclusive scan of the digit-major histogram (each wave scans one contiguous
-// segment with coalesced loads: a sum pass, a scan of the wave totals, a write pass), then the
-// skip flag of the pass (a digit holding all n keys) and the buffer the next pass reads.
-constexpr int SCAN_BLOCK = 1024;
-__global__ __launch_bounds__(SCAN_BLOCK) void k_srt_scan(SortBufs b, uint64_t n, uint32_t ntiles,
-                                                         uint32_t pass) {
-    constexpr uint32_t NW = SCAN_BLOCK / 64;
-    __shared__ uint32_t wsum[NW];
-    __shared__ uint32_t skip;
+// Offsets of a pass in two small steps. k_srt_scan_rows: one workgroup per digit turns the
+// digit's per-tile counts into exclusive prefixes and records the digit's total.
+// k_srt_scan_digits: one workgroup turns the 256 totals into each digit's first output position,
+// sets the pass's skip flag (one digit holds all n keys) and the buffer the next pass reads.
+__device__ inline uint32_t block_scan256(uint32_t v, uint32_t* wsum, uint32_t& total) {
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
-    const uint64_t E = (uint64_t)ntiles * 256;
-    const uint64_t seg = (((E + NW - 1) / NW) + 63) / 64 * 64;
-    const uint64_t lo = wv * seg < E ? wv * seg : E, hi = lo + seg < E ? lo + seg : E;
-    if (tid == 0) skip = 0;
-    constexpr int SCH = 32;
-    uint32_t s = 0;
-    for (uint64_t c0 = lo; c0 < hi; c0 += 64 * SCH) {
-        uint32_t v[SCH];
-#pragma unroll
-        for (int j = 0; j < SCH; ++j) {
-            const uint64_t e = c0 + (uint64_t)j * 64 + lane;
-            v[j] = e < hi ? b.hist[e] : 0u;
-        }
-#pragma unroll
-        for (int j = 0; j < SCH; ++j) s += v[j];
+    uint32_t inc = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o, 64);
+        if (lane >= (uint32_t)o) inc += y;
     }
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    if (lane == 0) wsum[wv] = s;
+    if (lane == 63) wsum[wv] = inc;
     __syncthreads();
+    uint32_t before = 0;
+    total = 0;
+    for (uint32_t k = 0; k < SRT_BLOCK / 64; ++k) {
+        if (k < wv) before += wsum[k];
+        total += wsum[k];
+    }
+    __syncthreads();
+    return before + inc - v;
+}
+
+__global__ __launch_bounds__(SRT_BLOCK) void k_srt_scan_rows(SortBufs b, uint32_t ntiles) {
+    __shared__ uint32_t wsum[SRT_BLOCK / 64];
+    uint32_t* row = b.hist + (uint64_t)blockIdx.x * ntiles;
     uint32_t carry = 0;
-    for (uint32_t k = 0; k < wv; ++k) carry += wsum[k];
-    // write pass in blocks of SCH groups: all SCH loads are issued before the first store
-    for (uint64_t c0 = lo; c0 < hi; c0 += 64 * SCH) {
-        uint32_t v[SCH];
-#pragma unroll
-        for (int j = 0; j < SCH; ++j) {
-            const uint64_t e = c0 + (uint64_t)j * 64 + lane;
-            v[j] = e < hi ? b.hist[e] : 0u;
-        }
-#pragma unroll
-        for (int j = 0; j < SCH; ++j) {
-            const uint64_t e = c0 + (uint64_t)j * 64 + lane;
-            uint32_t inc = v[j];
-            for (int o = 1; o < 64; o <<= 1) {
-                const uint32_t y = __shfl_up(inc, o, 64);
-                if (lane >= (uint32_t)o) inc += y;
-            }
-            if (e < hi) b.hist[e] = carry + inc - v[j];
-            carry += __shfl(inc, 63, 64);
-        }
+    for (uint32_t t0 = 0; t0 < ntiles; t0 += SRT_BLOCK) {
+        const uint32_t t = t0 + threadIdx.x;
+        const uint32_t v = t < ntiles ? row[t] : 0u;
+        uint32_t total;
+        const uint32_t ex = block_scan256(v, wsum, total);
+        if (t < ntiles) row[t] = carry + ex;
+        carry += total;
     }
+    if (threadIdx.x == 0) b.dstart[blockIdx.x] = carry;
+}
+
+__global__ __launch_bounds__(SRT_BLOCK) void k_srt_scan_digits(SortBufs b, uint64_t n, uint32_t pass) {
+    __shared__ uint32_t wsum[SRT_BLOCK / 64];
+    __shared__ uint32_t skip;
+    const uint32_t tid = threadIdx.x;
+    if (tid == 0) skip = 0;
+    const uint32_t tot = b.dstart[tid];
     __syncthreads();
-    // a digit's count is the difference of consecutive digit starts
-    if (tid < 256) {
-        const uint32_t a = b.hist[(uint64_t)tid * ntiles];
-        const uint64_t nxt = tid < 255 ? (uint64_t)b.hist[(uint64_t)(tid + 1) * ntiles] : n;
-        if (nxt - a == n) skip = 1;
-    }
-    __syncthreads();
+    if ((uint64_t)tot == n) skip = 1;
+    uint32_t all;
+    const uint32_t ex = block_scan256(tot, wsum, all);
+    b.dstart[tid] = ex;
     if (tid == 0) {
         const uint32_t src = b.ctl[4 + pass];
         b.ctl[pass] = skip;
@@ -368,7 +360,7 @@ __global__ __launch_bounds__(SRT_BLOCK) void k_srt_scatter(SortBufs b, uint64_t 
     const uint32_t* vin = b.vals[src];
     uint32_t* kout = b.keys[1u - src];
     uint32_t* vout = b.vals[1u - src];
-    run[tid] = b.hist[(uint64_t)tid * gridDim.x + blockIdx.x];
+    run[tid] = b.dstart[tid] + b.hist[(uint64_t)tid * gridDim.x + blockIdx.x];
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
     const uint64_t t0 = (uint64_t)blockIdx.x * SRT_TILE;
     for (uint32_t k = 0; k < SRT_KPT; ++k) {
@@ -605,7 +597,8 @@ static void scatter_add_sorted(const DevTable& t, DevLog* log, void* dst, uint64
     hipLaunchKernelGGL((k_srt_keys<G>), dim3(kgrid), dim3(SRT_BLOCK), 0, s, idx, n, rg, b);
     for (uint32_t p = 0; p < npasses; ++p) {
         hipLaunchKernelGGL(k_srt_hist, dim3(ntiles), dim3(SRT_BLOCK), 0, s, b, n, p);
-        hipLaunchKernelGGL(k_srt_scan, dim3(1), dim3(SCAN_BLOCK), 0, s, b, n, ntiles, p);
+        hipLaunchKernelGGL(k_srt_scan_rows, dim3(256), dim3(SRT_BLOCK), 0, s, b, ntiles);
+        hipLaunchKernelGGL(k_srt_scan_digits, dim3(1), dim3(SRT_BLOCK), 0, s, b, n, p);
         hipLaunchKernelGGL(k_srt_scatter, dim3(ntiles), dim3(SRT_BLOCK), 0, s, b, n, p);
     }
     const uint64_t waves = (n + RED_TILE - 1) / RED_TILE;
