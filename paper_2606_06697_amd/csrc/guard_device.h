@@ -83,8 +83,6 @@ struct DevLog {
     // scratch of one guarded launch, returned to its idle state by the launch's finishing kernel
     unsigned long long s_minkey;   // min over (elem << 2 | operand) of this launch's denials
     unsigned long long s_count;    // denials of this launch
-    unsigned int s_done;           // unused (kept for the layout)
-    unsigned int s_pad;
 };
 
 // Classification of `a` inside bucket b (split64[b] <= a is known): verdict + owner for a
@@ -146,47 +144,12 @@ __device__ inline void verdict_lane(const DevTable& t, uint64_t a, uint64_t len,
 
 // Wave-cooperative search for a wave-uniform address: each step compares 64 evenly spaced
 // splitters at once (ballot + popcount), shrinking the candidate range 64x per step.
-__device__ inline int64_t bucket_search_wave(const DevTable& t, uint64_t a) {
-    const uint32_t lane = __lane_id();
-    uint32_t lo = 0, cnt = t.nb;
-    if (cnt == 0) return -1;
-    while (true) {
-        uint32_t step = cnt <= 64 ? 1u : (cnt + 63u) / 64u;
-        uint32_t off = lane * step;
-        bool ok = off < cnt && t.split64[lo + off] <= a;
-        uint32_t c = (uint32_t)__popcll(__ballot(ok));
-        if (c == 0) return lo == 0 ? -1 : (int64_t)lo - 1;  // lo>0 cannot happen: split[lo] <= a
-        lo += (c - 1) * step;
-        if (step == 1) return lo;
-        uint32_t rest = cnt - (c - 1) * step;
-        cnt = rest < step ? rest : step;
-    }
-}
-
 // Move a wave-uniform 64-bit value into scalar registers (readfirstlane works on 32-bit
 // halves and returns int: widen through uint32_t so no sign bits leak into the high half).
 __device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
     const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
     return ((uint64_t)hi << 32) | lo;
-}
-
-// Binding of a kernel pointer argument (wave-uniform): the USER range containing p.
-__device__ inline Bind bind_wave(const DevTable& t, uint64_t p) {
-    Bind r{0, 0};
-    int64_t b = bucket_search_wave(t, p);
-    if (b < 0) return r;
-    PairRec rec = load_rec(t.rec + b);
-    const bool second = rec.base1 <= p;
-    const uint64_t end = second ? rec.end1 : rec.end0;
-    const uint32_t meta = second ? rec.meta1 : rec.meta0;
-    if (p < end && (meta & 3u) == KIND_USER) {
-        r.lo = second ? rec.base1 : t.split64[b];
-        r.hi = end;
-    }
-    r.lo = uniform_u64(r.lo);
-    r.hi = uniform_u64(r.hi);
-    return r;
 }
 
 // Reason recorded for a denied access at address a (already known to lie in [0, 2^64)).

@@ -213,8 +213,6 @@ __global__ void k_log_reset(DevLog* log) {
     log->reserved = 0;
     log->s_minkey = ~0ull;
     log->s_count = 0;
-    log->s_done = 0;
-    log->s_pad = 0;
 }
 
 hipError_t launch_log_reset(DevLog* log, hipStream_t s) {

@@ -127,3 +127,30 @@ def test_unguarded_sorted_scatter_add_matches_guarded(w, D):
     rc, f = tw.rt.fault_log(clear=True)
     assert f["count"] == 0
     tw.close()
+
+
+def test_sorted_scatter_add_suppress_only_leaves_log_empty():
+    """The SUPPRESS_ONLY policy on the sorted path: the same data as the oracle, no log entry,
+    and the call still takes a sequence number (a later logged call records the next one)."""
+    w, D = 4, 64
+    ar, tw, off = setup(w, D, 91)
+    rb = w * D
+    rng = random.Random(91)
+    base = ar.addr(off["dst"][0])
+    n = 40000
+    idx = indices(rng, n, DST_ROWS, [(ar.addr(off["prot"][0]) - base) // rb + 1])
+    ar.write(off["idx"][0], idx)
+    ol = G.FaultLog()
+    tw.g.agile_guarded_scatter(tw.h, base, rb, ar.addr(off["idx"][0]), ar.addr(off["src"][0]), n,
+                               0, 1, G.SUPPRESS_ONLY)
+    G.scatter_vec(tw.ot, ar.mem, ol, tw.next_seq(), base, rb, ar.addr(off["idx"][0]),
+                  ar.addr(off["src"][0]), n, w, True, G.SUPPRESS_ONLY)
+    ar.check("sorted scatter-add, suppress only")
+    log_matches(tw, ol, "sorted scatter-add, suppress only")
+    tw.g.agile_guarded_scatter(tw.h, base, rb, ar.addr(off["idx"][0]), ar.addr(off["src"][0]), n,
+                               0, 1)
+    G.scatter_vec(tw.ot, ar.mem, ol, tw.next_seq(), base, rb, ar.addr(off["idx"][0]),
+                  ar.addr(off["src"][0]), n, w, True)
+    ar.check("sorted scatter-add, logged after suppress only")
+    log_matches(tw, ol, "sorted scatter-add, logged after suppress only")
+    tw.close()
