@@ -238,6 +238,7 @@ def main():
     dt.close()
     torch.cuda.empty_cache()
     if not args.no_extras:
+        result["table_build"] = bench_table_build(g, tb)
         result["embedding"] = bench_embedding(g, args)
         torch.cuda.empty_cache()
         result["batch"] = bench_batch(g, args)
@@ -303,6 +304,45 @@ def measured_traffic(kernel, algorithmic):
         return int(vals["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def bench_table_build(g, tb):
+    """Host-side table maintenance: a bulk build of the 65,536-range table plus its first device
+    upload, and single inserts / removes through the C ABI followed by an upload."""
+    import numpy as np
+    import torch
+
+    reps = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rt = g.RangeTable(N_RANGES + 16)
+        rt.insert_many(tb.base, tb.size, tb.kind)
+        g.agile_rt_sync(rt.handle)
+        torch.cuda.synchronize()
+        reps.append(time.perf_counter() - t0)
+        rt.close()
+    bulk_ms = float(np.median(reps)) * 1e3
+    m = 4096
+    base, size, kind = tb.base[:m].tolist(), tb.size[:m].tolist(), tb.kind[:m].tolist()
+    rt = g.RangeTable(m + 16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ids = [rt.insert(b, s, k) for b, s, k in zip(base, size, kind)]
+    t1 = time.perf_counter()
+    for rid in ids[::4]:
+        rt.remove(rid)
+    t2 = time.perf_counter()
+    g.agile_rt_sync(rt.handle)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    rt.close()
+    return {"workload": "65536-range bulk build + upload; 4096 single inserts, 1024 removes, "
+                        "one upload (Python calling the C ABI)",
+            "bulk_build_upload_ms": round(bulk_ms, 3),
+            "single_inserts_per_s": round(m / (t1 - t0), 1),
+            "single_removes_per_s": round((m // 4) / (t2 - t1), 1),
+            "upload_after_edits_ms": round((t3 - t2) * 1e3, 3)}
 
 
 def bench_embedding(g, args):
