@@ -159,9 +159,12 @@ int agile_validate_ptrs(agile_rt* rt, const agile_ptr* d_q, uint64_t n, uint8_t*
                         int32_t* d_owner, void* stream);
 
 /* ---- guarded kernels (kernel memory guard, Section V-E) ----------------------------
- * Each pointer argument is bound once, on the device, to the USER range that contains
- * it (empty if none); every element access is then allowed only if it lies wholly inside
- * its argument's range. Each call takes the next sequence number of the handle. */
+ * Each pointer argument is bound once per call to the USER range that contains it (empty if
+ * none), looked up in the table as it stands when the call is made (the state the launch is
+ * ordered after); every element access is then allowed only if it lies wholly inside its
+ * argument's range. Each call takes the next sequence number of the handle. Calls on one
+ * handle must be ordered (one stream, or streams the caller synchronizes): they share the
+ * handle's fault-log scratch and, for scatter-add, its sort scratch. */
 
 /* dst[k] = src[k] for bytes k < nbytes. Denied src bytes read 0, denied dst bytes are left
  * unchanged. Any alignment; 16-byte-aligned pointers take the vector path. */
@@ -182,7 +185,12 @@ int agile_guarded_gather(agile_rt* rt, void* d_out, const void* d_table, uint64_
                          void* stream);
 
 /* dst[idx[i], :] = src[i, :] (accumulate == 0; with duplicate indices one writer wins) or
- * dst[idx[i], :] += src[i, :] (accumulate == 1, atomic adds in unspecified order). */
+ * dst[idx[i], :] += src[i, :] (accumulate == 1). With accumulate, calls of at least 32,768
+ * rows sort the destination rows (scratch owned by the handle, grown on demand with
+ * hipMalloc, freed by agile_rt_destroy; ENOMEM never results: without scratch the call takes
+ * the chunk path) and sum each run of equal rows in index order; the order in which partial
+ * sums of one row from different parts of the call are added is unspecified, as is the
+ * order in smaller calls (per-chunk sums, then atomic adds). */
 int agile_guarded_scatter(agile_rt* rt, void* d_dst, uint64_t row_bytes, const int64_t* d_idx,
                           const void* d_src, uint64_t n, int dtype, int accumulate, int policy,
                           void* stream);
@@ -193,7 +201,11 @@ int agile_guarded_scatter(agile_rt* rt, void* d_dst, uint64_t row_bytes, const i
  * later synchronization boundary, Section V-E), AGILE_OK when it is empty. */
 int agile_fault_log_read(agile_rt* rt, agile_fault* out, int clear, void* stream);
 
-/* ---- unguarded twins (same kernels with the guard compiled out; measurement only) ---- */
+/* ---- unguarded twins (same kernels with the guard compiled out; measurement only) ----
+ * Every access is performed as addressed: the caller guarantees the arguments are valid.
+ * agile_unguarded_scatter with accumulate == 1 and n >= 32,768 sorts 32-bit keys idx + 2^31,
+ * so its indices must lie in [-2^31, 2^31 - 1); its sort scratch is one buffer per device
+ * (grown on demand), so such calls on one device must be ordered. */
 int agile_unguarded_copy(void* d_dst, const void* d_src, uint64_t nbytes, void* stream);
 int agile_unguarded_triad(float* d_a, const float* d_b, const float* d_c, float s, uint64_t n,
                           void* stream);
