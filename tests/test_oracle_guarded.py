@@ -368,3 +368,47 @@ def test_fault_reason_codes():
     # suppressed loads read zero
     assert mem.read(addr["C"][0], 4) == bytes(4)
     assert ALLOW == 0
+
+
+def test_access_straddling_the_allocation_end_is_denied():
+    """The whole access must lie inside the binding (reading S9): an element whose first byte
+    is inside the allocation but whose last byte is not is denied, for triad and gather, and
+    its reason is STRADDLE on the own allocation. Values are derived by hand."""
+    t, mem = RangeTable(), Memory()
+    # b: a 10-byte allocation; elements at b+4 .. b+7 fit, b+8 .. b+11 runs past its end
+    t.insert(BASE, 10, USER)
+    mem.add(BASE, np.arange(10, dtype=np.uint8))
+    bvals = np.frombuffer(bytes(range(10)) + bytes(2), np.float32)
+    c = np.array([2.0, 3.0], np.float32)
+    t.insert(BASE + 64, 8, USER)
+    mem.add(BASE + 64, c.view(np.uint8))
+    t.insert(BASE + 128, 8, USER)
+    mem.add(BASE + 128, np.zeros(8, np.uint8))
+    for fn in (G.triad_loop, G.triad_vec):
+        log = RecordingLog() if fn is G.triad_loop else G.FaultLog()
+        mem.write(BASE + 128, bytes(8))
+        fn(t, mem, log, 5, BASE + 128, BASE + 4, BASE + 64, 1.0, 2)
+        got = np.frombuffer(mem.read(BASE + 128, 8), np.float32)
+        assert got[0] == np.float32(bvals[1] + np.float32(2.0))
+        assert got[1] == np.float32(3.0)                     # b[1] denied: reads 0
+        assert log.count == 1
+        f = log.first
+        assert (f["elem"], f["operand"], f["addr"], f["width"], f["verdict"], f["owner"]) == \
+            (1, 0, BASE + 8, 4, V_STRADDLE, 0)
+    # gather: the table's last row runs past the allocation end by two bytes
+    idx = np.array([0, 1, 2], np.int64)
+    t.insert(BASE + 256, 24, USER)
+    mem.add(BASE + 256, idx.view(np.uint8))
+    t.insert(BASE + 512, 12, USER)
+    mem.add(BASE + 512, np.zeros(12, np.uint8))
+    for fn in (G.gather_loop, G.gather_vec):
+        log = G.FaultLog()
+        mem.write(BASE + 512, bytes(12))
+        fn(t, mem, log, 6, BASE + 512, BASE + 1, 4, BASE + 256, 3, 4)
+        got = mem.read(BASE + 512, 12)
+        # rows [1,5) and [5,9) are inside the 10-byte allocation, row [9,13) runs past its end
+        assert got == bytes([1, 2, 3, 4]) + bytes([5, 6, 7, 8]) + bytes(4)
+        f = log.first
+        assert log.count == 1
+        assert (f["elem"], f["operand"], f["addr"], f["verdict"], f["owner"]) == \
+            (2, 1, BASE + 9, V_STRADDLE, 0)

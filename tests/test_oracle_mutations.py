@@ -1,0 +1,159 @@
+"""The oracle's pins catch plausible mistakes (CPU only).
+
+Each case plants one mistake in the oracle (monkeypatched for the duration of the test) and
+runs the pin tests that should notice it: the brute-force scan, the Table I fixture, the
+boundary invariants, the exact rational rounding of the triad, the loop-versus-vectorized
+agreement, the unit-gradient counts, the reason codes and the hand-derived straddling
+accesses. The unmodified oracle passes all of them; every planted mistake must make at least
+one of them fail (an assertion, or an error such as reading memory outside an allocation).
+"""
+import bisect
+
+import numpy as np
+import pytest
+
+import oracle.guarded as G
+from oracle.table import (RangeTable, ALLOW, V_PROTECTED, V_STRADDLE, V_UNMAPPED, USER,
+                          PROTECTED)
+import test_oracle_guarded as PG
+import test_oracle_table as PT
+
+
+def _fails(checks):
+    for fn in checks:
+        try:
+            fn()
+        except Exception:
+            return True
+    return False
+
+
+TABLE_CHECKS = ([PT.test_table1_fixture, PT.test_boundary_invariants] +
+                [lambda s=s: PT.test_brute_force_exhaustive_boundaries(s) for s in range(12)])
+
+GUARD_CHECKS = ([PG.test_access_straddling_the_allocation_end_is_denied,
+                 PG.test_triad_matches_exact_rational_rounding,
+                 PG.test_scatter_add_unit_gradient_counts, PG.test_fault_reason_codes,
+                 PG.test_gather_no_fault_is_take, PG.test_copy_partial_closed_form_values] +
+                [lambda s=s: PG.test_copy_vec_matches_loop(s) for s in range(6)] +
+                [lambda s=s: PG.test_triad_vec_matches_loop(s) for s in range(4)] +
+                [lambda s=s, w=w, D=D: PG.test_gather_vec_matches_loop(s, w, D)
+                 for s in range(3) for (w, D) in [(4, 1), (4, 3), (8, 2)]] +
+                [lambda s=s, a=a: PG.test_scatter_vec_matches_loop(s, a)
+                 for s in range(3) for a in (False, True)])
+
+
+# ---- planted mistakes in the classification --------------------------------------------
+def _verdict_with(fit=lambda L, room: L <= room, protected_kinds=None, owner_pos=False):
+    def verdict(self, addr, length):
+        addr, length = int(addr), int(length)
+        ent = self.owner_entry(addr)
+        if ent is None:
+            return V_UNMAPPED, -1
+        b, end, kind, rid = ent
+        if owner_pos:
+            rid = self._bases.index(b)
+        if (kind != USER) if protected_kinds is None else (kind in protected_kinds):
+            return V_PROTECTED, rid
+        if fit(max(length, 1), end - addr):
+            return ALLOW, rid
+        return V_STRADDLE, rid
+    return verdict
+
+
+def _owner_with(left=False, end_inclusive=False):
+    def owner_entry(self, addr):
+        a = int(addr)
+        k = (bisect.bisect_left if left else bisect.bisect_right)(self._bases, a) - 1
+        if k < 0:
+            return None
+        b = self._bases[k]
+        end, kind, rid = self._by_base[b]
+        if a < end or (end_inclusive and a == end):
+            return (b, end, kind, rid)
+        return None
+    return owner_entry
+
+
+TABLE_MUTANTS = {
+    "fit is strict (len < end - addr)": ("verdict", _verdict_with(fit=lambda L, room: L < room)),
+    "fit off by one (len <= end - addr + 1)": ("verdict",
+                                               _verdict_with(fit=lambda L, room: L <= room + 1)),
+    "MMIO treated as user memory": ("verdict", _verdict_with(protected_kinds=(PROTECTED,))),
+    "owner is the sorted position, not the id": ("verdict", _verdict_with(owner_pos=True)),
+    "owner search finds the range ending at addr": ("owner_entry", _owner_with(left=True)),
+    "range end counted as inside": ("owner_entry", _owner_with(end_inclusive=True)),
+}
+
+
+def test_unmodified_oracle_passes_every_pin():
+    assert not _fails(TABLE_CHECKS)
+    assert not _fails(GUARD_CHECKS)
+
+
+@pytest.mark.parametrize("name", sorted(TABLE_MUTANTS))
+def test_classification_mistake_is_caught(name, monkeypatch):
+    attr, fn = TABLE_MUTANTS[name]
+    monkeypatch.setattr(RangeTable, attr, fn)
+    assert _fails(TABLE_CHECKS), name
+
+
+# ---- planted mistakes in the guarded kernels --------------------------------------------
+def _triad_one_rounding(orig):
+    """The per-access triad with the product and the sum rounded once, together."""
+    def triad_vec(table, mem, log, seq, a, b, c, s, n, policy=G.SUPPRESS_LOG):
+        deny = G._Denier(table, log, seq, G.OP_TRIAD, policy)
+        ba, bb, bc = table.binding(a), table.binding(b), table.binding(c)
+        for i in range(n):
+            vals = []
+            for op_i, (p, bind) in enumerate(((b, bb), (c, bc))):
+                A = p + 4 * i
+                if G._allowed(bind, A, 4):
+                    vals.append(np.float64(G._f32(mem.read(A, 4))))
+                else:
+                    vals.append(np.float64(0.0))
+                    deny(i, op_i, A, 4)
+            r = np.float32(vals[0] + np.float64(np.float32(s)) * vals[1])
+            A = a + 4 * i
+            if G._allowed(ba, A, 4):
+                mem.write(A, r.tobytes())
+            else:
+                deny(i, 2, A, 4)
+    return triad_vec
+
+
+def _scatter_overwrites(orig):
+    def scatter_vec(table, mem, log, seq, dst, row_bytes, idx_ptr, src, n, w=4,
+                    accumulate=False, policy=G.SUPPRESS_LOG):
+        return orig(table, mem, log, seq, dst, row_bytes, idx_ptr, src, n, w, False, policy)
+    return scatter_vec
+
+
+def _reason_without_remap(table, A, w):
+    if A < 0 or A > G.U64_MAX:
+        return V_UNMAPPED, -1
+    return table.verdict(A, w)
+
+
+def _allowed_strict(bind, A, w):
+    return bind[0] <= A and A + w < bind[1]
+
+
+def _allowed_first_byte(bind, A, w):
+    return bind[0] <= A < bind[1]
+
+
+GUARD_MUTANTS = {
+    "triad rounded once (fused)": ("triad_vec", _triad_one_rounding),
+    "scatter-add overwrites": ("scatter_vec", _scatter_overwrites),
+    "reason keeps ALLOW for cross-allocation": ("reason", lambda orig: _reason_without_remap),
+    "access check excludes the last element": ("_allowed", lambda orig: _allowed_strict),
+    "access check tests the first byte only": ("_allowed", lambda orig: _allowed_first_byte),
+}
+
+
+@pytest.mark.parametrize("name", sorted(GUARD_MUTANTS))
+def test_guard_mistake_is_caught(name, monkeypatch):
+    attr, make = GUARD_MUTANTS[name]
+    monkeypatch.setattr(G, attr, make(getattr(G, attr)))
+    assert _fails(GUARD_CHECKS), name
