@@ -272,3 +272,51 @@ def test_unguarded_twins_match_guarded_on_valid_inputs():
     rc, f = g.rt.fault_log()
     assert rc == g.g.AGILE_OK
     g.close()
+
+
+def test_elements_straddling_an_allocation_end():
+    """Allocations whose ends fall inside an element: the element that straddles the end is
+    denied as a whole (its first bytes are inside), for triad, gather, scatter and
+    scatter-add, on both row kernels' fast and exact paths."""
+    need_gpu()
+    ar = Arena(1 << 16, 77)
+    tw = Twin(16)
+    X = (0x100, 0x100 + 1026)        # 256.5 floats
+    Y = (0x1000, 0x1000 + 4094)
+    Z = (0x3000, 0x3000 + 4096)
+    I = (0x5000, 0x5000 + 2048)
+    for lo, hi in (X, Y, Z, I):
+        tw.insert(ar.addr(lo), hi - lo, 0)
+    rng = np.random.default_rng(5)
+    for lo, hi in (X, Y, Z):
+        ar.write(lo, rng.integers(-50, 51, (hi - lo) // 4).astype(np.float32))
+    ol = G.FaultLog()
+    # triad: b runs out inside element 256
+    for n in (256, 257, 300):
+        tw.g.agile_guarded_triad(tw.h, ar.addr(Z[0]), ar.addr(X[0]), ar.addr(Y[0]), 2.0, n)
+        G.triad_vec(tw.ot, ar.mem, ol, tw.next_seq(), ar.addr(Z[0]), ar.addr(X[0]),
+                    ar.addr(Y[0]), 2.0, n)
+        ar.check(f"triad straddle n={n}")
+        log_matches(tw, ol, f"triad straddle n={n}")
+    # gather / scatter / scatter-add with rows of 8 bytes over X: row 128 straddles the end
+    idx = np.array([0, 127, 128, 5, 128, 129, -1, 64], dtype=np.int64)
+    ar.write(I[0], idx)
+    for D, dtype, w in ((2, 0, 4), (1, 1, 8), (4, 0, 4)):
+        rb = w * D
+        tw.g.agile_guarded_gather(tw.h, ar.addr(Z[0]), ar.addr(X[0]), rb, ar.addr(I[0]),
+                                  idx.size, dtype)
+        G.gather_vec(tw.ot, ar.mem, ol, tw.next_seq(), ar.addr(Z[0]), ar.addr(X[0]), rb,
+                     ar.addr(I[0]), idx.size, w)
+        ar.check(f"gather straddle D={D} w={w}")
+        log_matches(tw, ol, f"gather straddle D={D} w={w}")
+        for acc in (0, 1):
+            uniq = idx if acc else np.array([0, 127, 128, 5, 129, -1, 64, 3], dtype=np.int64)
+            ar.write(I[0], uniq)
+            tw.g.agile_guarded_scatter(tw.h, ar.addr(X[0]), rb, ar.addr(I[0]), ar.addr(Y[0]),
+                                       uniq.size, dtype, acc)
+            G.scatter_vec(tw.ot, ar.mem, ol, tw.next_seq(), ar.addr(X[0]), rb, ar.addr(I[0]),
+                          ar.addr(Y[0]), uniq.size, w, bool(acc))
+            ar.check(f"scatter straddle D={D} w={w} acc={acc}")
+            log_matches(tw, ol, f"scatter straddle D={D} w={w} acc={acc}")
+        ar.write(I[0], idx)
+    tw.close()
