@@ -14,8 +14,8 @@ namespace agile {
 
 constexpr int BBLOCK = 256;
 constexpr uint64_t TILE_PTRS = 2048;       // pointers per validation tile (8 per thread)
-constexpr uint64_t TILE_COPY = 1ull << 20; // bytes per copy tile
-constexpr int COPY_U = 16;                 // 16-byte vectors in flight per thread
+constexpr uint64_t TILE_COPY = 2ull << 20; // bytes per copy tile
+constexpr int COPY_U = 8;                 // 16-byte vectors in flight per thread
 constexpr uint64_t COPY_CHUNK = (uint64_t)BBLOCK * COPY_U * 16;  // one pass of a workgroup
 constexpr uint64_t TILE_ROWS = 16384;      // rows per gather tile
 constexpr int VQ = 8;
@@ -292,7 +292,7 @@ __global__ __launch_bounds__(BBLOCK) void k_batch(BatchArgs A) {
 
 hipError_t launch_batch(const BatchArgs& A, const DevInfo& d, hipStream_t s) {
     if (A.ntiles == 0) return hipSuccess;
-    uint64_t grid = (uint64_t)d.num_cu * 2;
+    uint64_t grid = (uint64_t)d.num_cu;
     if (grid > A.ntiles) grid = A.ntiles;
     hipLaunchKernelGGL(k_batch, dim3((uint32_t)grid), dim3(BBLOCK), 0, s, A);
     return hipGetLastError();
