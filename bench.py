@@ -167,6 +167,7 @@ def main():
         "triad_unguarded": lambda: g.agile_unguarded_triad(a_ref, b, c, 3.0, TRIAD_N),
         "gather": lambda: g.agile_guarded_gather(dt.handle, out, table, 4, idx, GATHER_N),
         "gather_unguarded": lambda: g.agile_unguarded_gather(out_ref, table, 4, idx, GATHER_N),
+        "validate_dma": lambda: g.agile_validate_dma(vt.handle, q, nq, verdict, owner),
     }, args.warmup, args.steps)
     dt.fault_log(clear=True)
     torch.cuda.synchronize()
@@ -214,7 +215,9 @@ def main():
                    "queries": nq, "ranges": N_RANGES, "triad_elems": TRIAD_N,
                    "gather_idx": GATHER_N, "gather_rows": GATHER_ROWS},
         "validations_per_s": round(nq / (t_v / 1e3), 1),
-        "kernel_ms": {"validate": round(t_v, 4), "triad": round(t_t, 4),
+        "dma_checks_per_s": round(nq / (med(twin["validate_dma"]) / 1e3), 1),
+        "kernel_ms": {"validate": round(t_v, 4), "validate_dma": round(med(twin["validate_dma"]), 4),
+                      "triad": round(t_t, 4),
                       "gather": round(t_g, 4), "triad_unguarded": round(ug_t, 4),
                       "gather_unguarded": round(ug_g, 4)},
         "guarded_gbps": {k: round(v, 1) for k, v in gbs.items()},

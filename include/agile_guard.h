@@ -49,7 +49,8 @@ enum {
     AGILE_ENOENT = -4,    /* unknown or already removed range id */
     AGILE_ENOSPC = -5,    /* table at capacity, or the id space (2^30 ids) is used up */
     AGILE_EDEVICE = -6,   /* a HIP runtime call or kernel launch failed */
-    AGILE_EFAULTED = -7   /* fault log is non-empty ("poison" surfaces here) */
+    AGILE_EFAULTED = -7,  /* fault log is non-empty ("poison" surfaces here) */
+    AGILE_ETRAPPED = -8   /* the handle was retired by a violation under AGILE_POLICY_TRAP */
 };
 
 /* Range kinds (Table I): user allocations, protected module/service memory, MMIO. */
@@ -59,18 +60,29 @@ enum { AGILE_KIND_USER = 0, AGILE_KIND_PROTECTED = 1, AGILE_KIND_MMIO = 2 };
  * MMIO owner -> PROTECTED; a USER owner -> ALLOW if max(len,1) <= end - addr, else
  * STRADDLE (the byte range must stay inside one live allocation, Section V-C).
  * CROSS_ALLOC only appears as a fault reason: a guarded access that lands in a different
- * user allocation than its argument's. */
+ * user allocation than its argument's. INEXACT only comes from agile_validate_dma. */
 enum {
     AGILE_ALLOW = 0,
     AGILE_V_PROTECTED = 1,
     AGILE_V_STRADDLE = 2,
     AGILE_V_UNMAPPED = 3,
-    AGILE_V_CROSS_ALLOC = 4
+    AGILE_V_CROSS_ALLOC = 4,
+    AGILE_V_INEXACT = 5
 };
 
 /* Guard policies (Section V-E): SUPPRESS_LOG = sink to a zero page + poison record;
- * SUPPRESS_ONLY = sink without a record. */
-enum { AGILE_POLICY_SUPPRESS_LOG = 0, AGILE_POLICY_SUPPRESS_ONLY = 1 };
+ * SUPPRESS_ONLY = sink without a record; TRAP = stop on a violation and retire the context
+ * (Section V-E "trap"; Section IV-D: a worker whose context can no longer be trusted is
+ * retired). A GPU trap instruction would end every kernel of the process, so TRAP is realized
+ * at call granularity: the call runs as under SUPPRESS_LOG (no denied access happens, every
+ * denial is counted and the smallest key recorded), then waits for its stream; if it denied
+ * at least one access, the handle is retired and the call returns AGILE_ETRAPPED. A TRAP call
+ * therefore synchronizes its stream (it cannot be captured in a graph). A retired handle
+ * accepts no further work: validation, guarded calls, insertions, agile_rt_sync and batches
+ * naming it return AGILE_ETRAPPED before queuing anything; agile_rt_remove (revocation),
+ * agile_rt_count, agile_fault_log_read (which then returns AGILE_ETRAPPED) and
+ * agile_rt_destroy still work. Retirement lasts until the handle is destroyed. */
+enum { AGILE_POLICY_SUPPRESS_LOG = 0, AGILE_POLICY_SUPPRESS_ONLY = 1, AGILE_POLICY_TRAP = 2 };
 
 /* Guarded operations, as recorded in a fault record. */
 enum {
@@ -158,6 +170,14 @@ int agile_rt_sync(agile_rt* rt, void* stream);
 int agile_validate_ptrs(agile_rt* rt, const agile_ptr* d_q, uint64_t n, uint8_t* d_verdict,
                         int32_t* d_owner, void* stream);
 
+/* DMA registration check (Section V-C: a module may register a user buffer for device DMA
+ * only if it is an exact live user allocation). Same arguments, layout and errors as
+ * agile_validate_ptrs; each query gets the pointer verdict, except that an ALLOW range which is
+ * not a whole USER range (addr != base or len != size; len is taken as given, so 0 is never
+ * exact) gets AGILE_V_INEXACT. The owner is reported as in agile_validate_ptrs. */
+int agile_validate_dma(agile_rt* rt, const agile_ptr* d_q, uint64_t n, uint8_t* d_verdict,
+                       int32_t* d_owner, void* stream);
+
 /* ---- guarded kernels (kernel memory guard, Section V-E) ----------------------------
  * Each pointer argument is bound once per call to the USER range that contains it (empty if
  * none), looked up in the table as it stands when the call is made (the state the launch is
@@ -196,9 +216,10 @@ int agile_guarded_scatter(agile_rt* rt, void* d_dst, uint64_t row_bytes, const i
                           void* stream);
 
 /* Read the fault log (queues a device-to-host copy on `stream` and synchronizes it).
- * *out receives the log; clear != 0 then resets it on `stream`. Returns AGILE_EFAULTED when
- * the log holds at least one denial (the paper's "poison" policy reports a violation at a
- * later synchronization boundary, Section V-E), AGILE_OK when it is empty. */
+ * *out receives the log; clear != 0 then resets it on `stream`. Returns AGILE_ETRAPPED when
+ * the handle is retired, else AGILE_EFAULTED when the log holds at least one denial (the
+ * paper's "poison" policy reports a violation at a later synchronization boundary, Section
+ * V-E), AGILE_OK when it is empty. */
 int agile_fault_log_read(agile_rt* rt, agile_fault* out, int clear, void* stream);
 
 /* ---- unguarded twins (same kernels with the guard compiled out; measurement only) ----

@@ -23,5 +23,6 @@ that decides which fault is "first").
 """
 from .table import (  # noqa: F401
     RangeTable, OverlapError, ALLOW, V_PROTECTED, V_STRADDLE, V_UNMAPPED, V_CROSS_ALLOC,
+    V_INEXACT,
     USER, PROTECTED, MMIO, U64_MAX,
 )

@@ -8,7 +8,7 @@ which is equivalent because entries are intervals.
 """
 from __future__ import annotations
 
-from .table import ALLOW, V_PROTECTED, V_STRADDLE, V_UNMAPPED, USER, U64_MAX
+from .table import ALLOW, V_PROTECTED, V_STRADDLE, V_UNMAPPED, V_INEXACT, USER, U64_MAX
 
 
 def owner_scan(entries, a: int):
@@ -36,3 +36,13 @@ def verdict_brute(entries, addr: int, length: int):
         if owner_scan(entries, a) is not first:
             return V_STRADDLE, first[3]
     return ALLOW, first[3]
+
+
+def dma_verdict_brute(entries, addr: int, length: int):
+    """DMA registration by its definition: accepted iff some USER entry is exactly
+    [addr, addr + length); otherwise the pointer verdict, with ALLOW reported as INEXACT."""
+    for b, e, kind, rid in entries:
+        if kind == USER and b == addr and e - b == length:
+            return ALLOW, rid
+    v, rid = verdict_brute(entries, addr, length)
+    return (V_INEXACT if v == ALLOW else v), rid

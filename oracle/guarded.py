@@ -22,6 +22,14 @@ redirects the access to quarantine memory. This module restates that guard per a
   of ``[A, A+w)`` with ALLOW replaced by CROSS_ALLOC, or UNMAPPED when ``A`` lies outside
   ``[0, 2**64)``.
 
+Policies: ``SUPPRESS_LOG`` (the ``sink`` to a zero page plus the ``poison`` record),
+``SUPPRESS_ONLY`` (the sink alone) and ``TRAP``. The paper's ``trap`` stops at a violation and
+may leave the worker's context unusable, so the worker is retired (Section V-E; Section IV-D,
+lifetime and revocation). Restated per call (``guarded_call``): a call of a retired handle does
+nothing and reports ``ETRAPPED``; a ``TRAP`` call runs as under ``SUPPRESS_LOG`` (the denied
+access never happens and is logged), and if it denied anything the handle is retired and the
+call reports ``ETRAPPED``.
+
 Access widths and orders: copy - bytes, src(0) then dst(1); triad ``a = b + s*c`` - fp32
 elements, b(0), c(1), a(2), computed as two float32 roundings (no fused multiply-add);
 gather ``out[i,:] = T[idx[i],:]`` - the 8-byte index load (elem ``i*D``), then per column
@@ -39,7 +47,8 @@ import numpy as np
 from .table import ALLOW, V_CROSS_ALLOC, V_UNMAPPED, U64_MAX
 
 OP_COPY, OP_TRIAD, OP_GATHER, OP_SCATTER, OP_SCATTER_ADD = 1, 2, 3, 4, 5
-SUPPRESS_LOG, SUPPRESS_ONLY = 0, 1
+SUPPRESS_LOG, SUPPRESS_ONLY, TRAP = 0, 1, 2
+OK, ETRAPPED = 0, -8
 _DT = {4: np.float32, 8: np.float64}
 
 
@@ -59,6 +68,7 @@ class FaultLog:
     def __init__(self):
         self.count = 0
         self.first = None
+        self.retired = False          # set by a violation under TRAP; clearing keeps it
 
     def clear(self):
         self.count = 0
@@ -84,14 +94,30 @@ def _allowed(bind, A, w):
 
 class _Denier:
     def __init__(self, table, log, seq, op, policy):
-        if policy not in (SUPPRESS_LOG, SUPPRESS_ONLY):
+        if policy not in (SUPPRESS_LOG, SUPPRESS_ONLY, TRAP):
             raise ValueError("unknown policy")
         self.t, self.log, self.seq, self.op = table, log, seq, op
-        self.on = policy == SUPPRESS_LOG
+        self.on = policy != SUPPRESS_ONLY
 
     def __call__(self, elem, operand, A, w):
         if self.on:
             self.log.offer(self.t, self.seq, elem, operand, A, w, self.op)
+
+
+def guarded_call(kernel, table, mem, log, seq, *args, policy=SUPPRESS_LOG, **kw):
+    """One guarded call of a handle whose log is ``log``, under any policy; returns the status.
+
+    ``kernel`` is one of the ``*_loop`` / ``*_vec`` functions below. A retired handle runs
+    nothing. Under ``TRAP`` a call that denied at least one access retires the handle.
+    """
+    if log.retired:
+        return ETRAPPED
+    before = log.count
+    kernel(table, mem, log, seq, *args, policy=policy, **kw)
+    if policy == TRAP and log.count != before:
+        log.retired = True
+        return ETRAPPED
+    return OK
 
 
 # ------------------------------------------------------------------ per-access loops

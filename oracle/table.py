@@ -15,6 +15,10 @@ Readings where the paper is silent:
 * the length test is ``max(len,1) <= end - addr`` (no overflow of ``addr + len``).
 * ranges are half-open ``[base, base+size)`` with ``size >= 1`` and ``base + size <= 2**64-1``.
 * MMIO and module-protected ranges both classify as PROTECTED.
+* DMA registration (Section V-C: accepted only for an exact live user allocation) uses the
+  same classification, except that an allowed range which is not the whole allocation
+  (``addr != base`` or ``len != size``, the length taken as given, so zero is never exact)
+  gets the code INEXACT=5.
 """
 from __future__ import annotations
 
@@ -23,6 +27,7 @@ import bisect
 import numpy as np
 
 ALLOW, V_PROTECTED, V_STRADDLE, V_UNMAPPED, V_CROSS_ALLOC = 0, 1, 2, 3, 4
+V_INEXACT = 5
 USER, PROTECTED, MMIO = 0, 1, 2
 U64_MAX = (1 << 64) - 1
 
@@ -129,6 +134,28 @@ class RangeTable:
         v[fits] = ALLOW
         v[strad] = V_STRADDLE
         owner[inside] = ids[jc[inside]]
+        return v, owner
+
+    def dma_verdict(self, addr: int, length: int):
+        """DMA registration check -> (verdict, owner id): ALLOW only when [addr, addr+length)
+        is exactly a live USER allocation."""
+        v, rid = self.verdict(addr, length)
+        if v == ALLOW:
+            b, end, _, _ = self.owner_entry(addr)
+            if int(addr) != b or int(length) != end - b:
+                v = V_INEXACT
+        return v, rid
+
+    def dma_verdict_many(self, addr: np.ndarray, length: np.ndarray):
+        """Vectorized ``dma_verdict``."""
+        addr = np.asarray(addr, dtype=np.uint64)
+        length = np.asarray(length, dtype=np.uint64)
+        v, owner = self.verdict_many(addr, length)
+        base, end, _, _ = self.arrays()
+        if base.size:
+            jc = np.maximum(np.searchsorted(base, addr, side="right").astype(np.int64) - 1, 0)
+            exact = (addr == base[jc]) & (length == end[jc] - base[jc])
+            v[(v == ALLOW) & ~exact] = V_INEXACT
         return v, owner
 
     def binding(self, p: int):

@@ -22,7 +22,7 @@ namespace agile {
 
 constexpr uint32_t KIND_USER = 0;
 constexpr uint8_t V_ALLOW = 0, V_PROTECTED = 1, V_STRADDLE = 2, V_UNMAPPED = 3,
-                  V_CROSS_ALLOC = 4;
+                  V_CROSS_ALLOC = 4, V_INEXACT = 5;
 constexpr uint64_t U64MAX = ~0ull;
 
 struct alignas(32) PairRec {

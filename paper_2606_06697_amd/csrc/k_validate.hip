@@ -10,6 +10,10 @@
 // greater, so the predicate stays monotone and needs no bound checks), and one bucket record
 // read resolves the range inside the bucket with its end, id and kind.
 //
+// With DMA set the same search answers the DMA registration check (Section V-C: only an exact
+// live user allocation is accepted): an allowed range that is not the whole allocation, from
+// its base with its full size, is reported INEXACT.
+//
 // Two record formats: packed 16-byte records (one load per query; offsets relative to the
 // bucket base, used whenever the table's offsets fit) and general 32-byte records. Queries
 // stream in with coalesced 16-byte loads, the next chunk's queries are in flight while the
@@ -91,7 +95,7 @@ __device__ __forceinline__ void keys_and_starts(const DevTable& t, const uint32_
 }
 
 // ---------------------------------------------------------------- general (32-byte records)
-template <bool COMP, int QPT, bool TAIL>
+template <bool COMP, int QPT, bool TAIL, bool DMA>
 __device__ __forceinline__ void chunk_wide(const DevTable& t, const unsigned char* lds_raw,
                                            const uint32_t* ri, const ulonglong2 (&x)[QPT],
                                            uint64_t n, uint8_t* __restrict__ verdict,
@@ -144,6 +148,13 @@ __device__ __forceinline__ void chunk_wide(const DevTable& t, const unsigned cha
         int32_t o = -1;
         const uint64_t L = x[j].y;
         if (found[j]) classify_in_bucket(rec[j], x[j].x, L < 1 ? 1 : L, v, o);
+        if (DMA && v == V_ALLOW) {
+            // the first range of a bucket starts at the bucket's splitter
+            const bool second = rec[j].base1 <= x[j].x;
+            const uint64_t st = second ? rec[j].base1 : t.split64[b[j]];
+            const uint64_t en = second ? rec[j].end1 : rec[j].end0;
+            if (x[j].x != st || L != en - st) v = V_INEXACT;
+        }
         const uint64_t i = c0 + (uint64_t)j * 64u + lane;
         if (!TAIL || i < n) {
             verdict[i] = v;
@@ -155,7 +166,7 @@ __device__ __forceinline__ void chunk_wide(const DevTable& t, const unsigned cha
 // ---------------------------------------------------------------- packed 16-byte records
 // Offsets inside a bucket (the second range's base, both ends) are below 2^32 whenever packed
 // records are built, so after one 64-bit subtraction the classification runs on 32-bit values.
-template <bool COMP, int LEVELS, int QPT, bool TAIL>
+template <bool COMP, int LEVELS, int QPT, bool TAIL, bool DMA>
 __device__ __forceinline__ void chunk_packed(const DevTable& t, const unsigned char* lds_raw,
                                              const uint32_t* ri, const ulonglong2 (&x)[QPT],
                                              uint64_t n, uint8_t* __restrict__ verdict,
@@ -209,9 +220,13 @@ __device__ __forceinline__ void chunk_packed(const DevTable& t, const unsigned c
         const bool inside = found[j] && near && rel < oend;
         // inside a range, oend - rel >= 1, so max(len, 1) <= oend - rel iff len <= oend - rel
         const bool fits = (uint32_t)(x[j].y >> 32) == 0u && (uint32_t)x[j].y <= oend - rel;
+        // DMA: the range starts at offset 0 (first) or ob1 (second) and must be taken whole
+        const uint32_t ost = second ? ob1 : 0u;
+        const bool exact = !DMA || (rel == ost && (uint32_t)x[j].y == oend - ost);
         const uint8_t v = !inside ? V_UNMAPPED
-                                  : ((meta & 3u) != KIND_USER ? V_PROTECTED
-                                                              : (fits ? V_ALLOW : V_STRADDLE));
+                                  : ((meta & 3u) != KIND_USER
+                                         ? V_PROTECTED
+                                         : (fits ? (exact ? V_ALLOW : V_INEXACT) : V_STRADDLE));
         const int32_t o = inside ? (int32_t)(meta >> 2) : -1;
         if (TAIL) {
             const uint64_t i = c0 + (uint64_t)j * 64u + lane;
@@ -227,7 +242,7 @@ __device__ __forceinline__ void chunk_packed(const DevTable& t, const unsigned c
 }
 
 // Grid-stride loop over chunks of 64*QPT queries per wave, full chunks software-pipelined.
-template <bool COMP, bool PACKED, int LEVELS, int QPT>
+template <bool COMP, bool PACKED, int LEVELS, int QPT, bool DMA>
 __global__ __launch_bounds__(VBLOCK) void k_validate(DevTable t, const ulonglong2* __restrict__ q,
                                                       uint64_t n, uint8_t* __restrict__ verdict,
                                                       int32_t* __restrict__ owner) {
@@ -257,23 +272,24 @@ __global__ __launch_bounds__(VBLOCK) void k_validate(DevTable t, const ulonglong
         for (int j = 0; j < QPT; ++j) cur[j] = x[j];
         if (c0 + stride < nfull) load_chunk<QPT, false>(q, n, c0 + stride, lane, x);
         if (PACKED)
-            chunk_packed<COMP, LEVELS, QPT, false>(t, lds_raw, ri, cur, n, verdict, owner, c0, lane);
+            chunk_packed<COMP, LEVELS, QPT, false, DMA>(t, lds_raw, ri, cur, n, verdict, owner, c0,
+                                                        lane);
         else
-            chunk_wide<COMP, QPT, false>(t, lds_raw, ri, cur, n, verdict, owner, c0, lane);
+            chunk_wide<COMP, QPT, false, DMA>(t, lds_raw, ri, cur, n, verdict, owner, c0, lane);
     }
     if (c0 < n) {
         load_chunk<QPT, true>(q, n, c0, lane, x);
         if (PACKED)
-            chunk_packed<COMP, LEVELS, QPT, true>(t, lds_raw, ri, x, n, verdict, owner, c0, lane);
+            chunk_packed<COMP, LEVELS, QPT, true, DMA>(t, lds_raw, ri, x, n, verdict, owner, c0, lane);
         else
-            chunk_wide<COMP, QPT, true>(t, lds_raw, ri, x, n, verdict, owner, c0, lane);
+            chunk_wide<COMP, QPT, true, DMA>(t, lds_raw, ri, x, n, verdict, owner, c0, lane);
     }
 }
 
-template <bool COMP, bool PACKED, int LEVELS, int QPT>
+template <bool COMP, bool PACKED, int LEVELS, int QPT, bool DMA>
 static hipError_t launch_v(const DevTable& t, const DevInfo& d, const void* q, uint64_t n,
                            uint8_t* verdict, int32_t* owner, hipStream_t s) {
-    const void* fn = reinterpret_cast<const void*>(&k_validate<COMP, PACKED, LEVELS, QPT>);
+    const void* fn = reinterpret_cast<const void*>(&k_validate<COMP, PACKED, LEVELS, QPT, DMA>);
     const size_t lds = t.lds_bytes;
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)(lds > 0 ? lds : 16));
@@ -286,33 +302,37 @@ static hipError_t launch_v(const DevTable& t, const DevInfo& d, const void* q, u
     const uint64_t want = (chunks + (VBLOCK / 64) - 1) / (VBLOCK / 64);
     uint64_t grid = (uint64_t)d.num_cu * per_cu;
     if (want < grid) grid = want;
-    hipLaunchKernelGGL((k_validate<COMP, PACKED, LEVELS, QPT>), dim3((uint32_t)grid), dim3(VBLOCK),
+    hipLaunchKernelGGL((k_validate<COMP, PACKED, LEVELS, QPT, DMA>), dim3((uint32_t)grid), dim3(VBLOCK),
                        lds, s, t, reinterpret_cast<const ulonglong2*>(q), n, verdict, owner);
     return hipGetLastError();
 }
 
-template <bool COMP>
+template <bool COMP, bool DMA>
 static hipError_t launch_c(const DevTable& t, const DevInfo& d, const void* q, uint64_t n,
                            uint8_t* verdict, int32_t* owner, hipStream_t s) {
     constexpr int QW = 6;  // queries per lane, general records
     constexpr int QP = 6;  // queries per lane, packed records
     if (t.narrow && t.rlog2 == 0) {
         switch (t.lift) {
-            case 2: return launch_v<COMP, true, 2, QP>(t, d, q, n, verdict, owner, s);
-            case 4: return launch_v<COMP, true, 4, QP>(t, d, q, n, verdict, owner, s);
-            case 6: return launch_v<COMP, true, 6, QP>(t, d, q, n, verdict, owner, s);
-            case 8: return launch_v<COMP, true, 8, QP>(t, d, q, n, verdict, owner, s);
+            case 2: return launch_v<COMP, true, 2, QP, DMA>(t, d, q, n, verdict, owner, s);
+            case 4: return launch_v<COMP, true, 4, QP, DMA>(t, d, q, n, verdict, owner, s);
+            case 6: return launch_v<COMP, true, 6, QP, DMA>(t, d, q, n, verdict, owner, s);
+            case 8: return launch_v<COMP, true, 8, QP, DMA>(t, d, q, n, verdict, owner, s);
             default: break;
         }
     }
-    return launch_v<COMP, false, 0, QW>(t, d, q, n, verdict, owner, s);
+    return launch_v<COMP, false, 0, QW, DMA>(t, d, q, n, verdict, owner, s);
 }
 
 hipError_t launch_validate(const DevTable& t, const DevInfo& d, const void* q, uint64_t n,
-                           uint8_t* verdict, int32_t* owner, hipStream_t s) {
+                           uint8_t* verdict, int32_t* owner, bool dma, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    if (t.compressed) return launch_c<true>(t, d, q, n, verdict, owner, s);
-    return launch_c<false>(t, d, q, n, verdict, owner, s);
+    if (dma) {
+        if (t.compressed) return launch_c<true, true>(t, d, q, n, verdict, owner, s);
+        return launch_c<false, true>(t, d, q, n, verdict, owner, s);
+    }
+    if (t.compressed) return launch_c<true, false>(t, d, q, n, verdict, owner, s);
+    return launch_c<false, false>(t, d, q, n, verdict, owner, s);
 }
 
 }  // namespace agile

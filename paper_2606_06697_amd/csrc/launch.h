@@ -16,8 +16,9 @@ struct DevInfo {
 // Maximum number of radix entries (plus one) the validation index may use.
 constexpr uint32_t MAX_RADIX = (1u << 14) + 1;
 
+// dma: answer the DMA registration check (only a whole USER range is ALLOW, else INEXACT).
 hipError_t launch_validate(const DevTable& t, const DevInfo& d, const void* q, uint64_t n,
-                           uint8_t* verdict, int32_t* owner, hipStream_t s);
+                           uint8_t* verdict, int32_t* owner, bool dma, hipStream_t s);
 
 // Guarded launches take the bindings of their pointer arguments, looked up on the host from the
 // table the launch is ordered after (`binds` in the operand order of the operation: copy src,

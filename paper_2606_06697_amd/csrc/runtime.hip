@@ -69,6 +69,8 @@ struct agile_rt {
     void* hstage = nullptr;
     size_t stage_bytes = 0;
     agile_fault* hlog = nullptr;
+    unsigned long long* htrap = nullptr;  // log count before / after a TRAP-policy call
+    bool retired = false;                 // retired by a TRAP-policy violation
     hipEvent_t upload_done = nullptr;
     bool upload_pending = false;
     std::vector<hipStream_t> streams_used;
@@ -329,6 +331,7 @@ const char* agile_strerror(int code) {
         case AGILE_ENOSPC: return "range table full";
         case AGILE_EDEVICE: return "HIP runtime error";
         case AGILE_EFAULTED: return "guarded access denied (fault log not empty)";
+        case AGILE_ETRAPPED: return "handle retired by a violation under the trap policy";
         default: return "unknown status";
     }
 }
@@ -375,6 +378,8 @@ int agile_rt_create(agile_rt** out, uint32_t capacity, int device) {
     if (hipHostMalloc(&rt->hstage, rt->stage_bytes, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&rt->hlog), sizeof(agile_fault),
                       hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&rt->htrap), 2 * sizeof(unsigned long long),
+                      hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&rt->upload_done, hipEventDisableTiming) != hipSuccess) {
         agile_rt_destroy(rt);
         return AGILE_ENOMEM;
@@ -396,6 +401,7 @@ int agile_rt_destroy(agile_rt* rt) {
     if (rt->upload_done) (void)hipEventDestroy(rt->upload_done);
     if (rt->hstage) (void)hipHostFree(rt->hstage);
     if (rt->hlog) (void)hipHostFree(rt->hlog);
+    if (rt->htrap) (void)hipHostFree(rt->htrap);
     if (rt->dmem) (void)hipFree(rt->dmem);
     if (rt->sa_scratch) (void)hipFree(rt->sa_scratch);
     delete rt;
@@ -409,6 +415,7 @@ static int check_range(uint64_t base, uint64_t size, uint32_t kind) {
 
 int agile_rt_insert(agile_rt* rt, uint64_t base, uint64_t size, uint32_t kind, int32_t* out_id) {
     if (!rt) return AGILE_EINVAL;
+    if (rt->retired) return AGILE_ETRAPPED;
     int rc = check_range(base, size, kind);
     if (rc != AGILE_OK) return rc;
     if (rt->entries.size() >= rt->capacity || rt->next_id > MAX_ID) return AGILE_ENOSPC;
@@ -429,6 +436,7 @@ int agile_rt_insert(agile_rt* rt, uint64_t base, uint64_t size, uint32_t kind, i
 int agile_rt_insert_many(agile_rt* rt, const uint64_t* base, const uint64_t* size,
                          const uint8_t* kind, uint32_t n, int32_t* out_ids) {
     if (!rt) return AGILE_EINVAL;
+    if (rt->retired) return AGILE_ETRAPPED;
     if (n == 0) return AGILE_OK;
     if (!base || !size || !kind) return AGILE_EINVAL;
     for (uint32_t i = 0; i < n; ++i) {
@@ -484,14 +492,16 @@ int agile_rt_count(const agile_rt* rt, uint32_t* out_n) {
 
 int agile_rt_sync(agile_rt* rt, void* stream) {
     if (!rt) return AGILE_EINVAL;
+    if (rt->retired) return AGILE_ETRAPPED;
     DeviceGuard dg(rt->device);
     if (!dg.ok) return AGILE_EDEVICE;
     return prepare(rt, static_cast<hipStream_t>(stream));
 }
 
-int agile_validate_ptrs(agile_rt* rt, const agile_ptr* d_q, uint64_t n, uint8_t* d_verdict,
-                        int32_t* d_owner, void* stream) {
+static int validate_common(agile_rt* rt, const agile_ptr* d_q, uint64_t n, uint8_t* d_verdict,
+                           int32_t* d_owner, bool dma, void* stream) {
     if (!rt) return AGILE_EINVAL;
+    if (rt->retired) return AGILE_ETRAPPED;
     if (n == 0) return AGILE_OK;
     if (!d_q || !d_verdict || !d_owner || ((uint64_t)d_q & 15)) return AGILE_EINVAL;
     DeviceGuard dg(rt->device);
@@ -499,13 +509,49 @@ int agile_validate_ptrs(agile_rt* rt, const agile_ptr* d_q, uint64_t n, uint8_t*
     hipStream_t s = static_cast<hipStream_t>(stream);
     int rc = prepare(rt, s);
     if (rc != AGILE_OK) return rc;
-    if (launch_validate(rt->tab, rt->info, d_q, n, d_verdict, d_owner, s) != hipSuccess)
+    if (launch_validate(rt->tab, rt->info, d_q, n, d_verdict, d_owner, dma, s) != hipSuccess)
         return AGILE_EDEVICE;
     return AGILE_OK;
 }
 
+int agile_validate_ptrs(agile_rt* rt, const agile_ptr* d_q, uint64_t n, uint8_t* d_verdict,
+                        int32_t* d_owner, void* stream) {
+    return validate_common(rt, d_q, n, d_verdict, d_owner, false, stream);
+}
+
+int agile_validate_dma(agile_rt* rt, const agile_ptr* d_q, uint64_t n, uint8_t* d_verdict,
+                       int32_t* d_owner, void* stream) {
+    return validate_common(rt, d_q, n, d_verdict, d_owner, true, stream);
+}
+
 static bool policy_ok(int policy) {
-    return policy == AGILE_POLICY_SUPPRESS_LOG || policy == AGILE_POLICY_SUPPRESS_ONLY;
+    return policy == AGILE_POLICY_SUPPRESS_LOG || policy == AGILE_POLICY_SUPPRESS_ONLY ||
+           policy == AGILE_POLICY_TRAP;
+}
+
+// Whether a call's denials go to the log (every policy but SUPPRESS_ONLY).
+static int log_on(int policy) { return policy != AGILE_POLICY_SUPPRESS_ONLY; }
+
+// Trap policy, before the call's kernels: queue a copy of the log's denial count.
+static int trap_begin(agile_rt* rt, int policy, hipStream_t s) {
+    if (policy != AGILE_POLICY_TRAP) return AGILE_OK;
+    return hipMemcpyAsync(&rt->htrap[0], &rt->d_log->count, sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost, s) == hipSuccess
+               ? AGILE_OK
+               : AGILE_EDEVICE;
+}
+
+// Trap policy, after the call's kernels: wait for them; if the count grew, the call denied an
+// access, so the handle is retired.
+static int trap_end(agile_rt* rt, int policy, hipStream_t s) {
+    if (policy != AGILE_POLICY_TRAP) return AGILE_OK;
+    if (hipMemcpyAsync(&rt->htrap[1], &rt->d_log->count, sizeof(unsigned long long),
+                       hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return AGILE_EDEVICE;
+    if (rt->htrap[1] == rt->htrap[0]) return AGILE_OK;
+    rt->retired = true;
+    return AGILE_ETRAPPED;
 }
 
 // Scratch of the sorted scatter-add, grown on demand; the old buffer is released only after the
@@ -543,22 +589,26 @@ static Bind host_bind(const agile_rt* rt, uint64_t p) {
 int agile_guarded_copy(agile_rt* rt, void* d_dst, const void* d_src, uint64_t nbytes, int policy,
                        void* stream) {
     if (!rt || !policy_ok(policy)) return AGILE_EINVAL;
+    if (rt->retired) return AGILE_ETRAPPED;
     DeviceGuard dg(rt->device);
     if (!dg.ok) return AGILE_EDEVICE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     int rc = prepare(rt, s);
     if (rc != AGILE_OK) return rc;
+    rc = trap_begin(rt, policy, s);
+    if (rc != AGILE_OK) return rc;
     const unsigned long long seq = rt->seq++;
     const Bind b[2] = {host_bind(rt, (uint64_t)d_src), host_bind(rt, (uint64_t)d_dst)};
     if (launch_copy(true, rt->tab, rt->d_log, b, d_dst, d_src, nbytes, seq,
-                    policy == AGILE_POLICY_SUPPRESS_LOG, rt->info, s) != hipSuccess)
+                    log_on(policy), rt->info, s) != hipSuccess)
         return AGILE_EDEVICE;
-    return AGILE_OK;
+    return trap_end(rt, policy, s);
 }
 
 int agile_guarded_triad(agile_rt* rt, float* d_a, const float* d_b, const float* d_c, float s_,
                         uint64_t n, int policy, void* stream) {
     if (!rt || !policy_ok(policy)) return AGILE_EINVAL;
+    if (rt->retired) return AGILE_ETRAPPED;
     if ((((uint64_t)d_a | (uint64_t)d_b | (uint64_t)d_c) & 3) || n > (U64MAX >> 3))
         return AGILE_EINVAL;
     DeviceGuard dg(rt->device);
@@ -566,13 +616,15 @@ int agile_guarded_triad(agile_rt* rt, float* d_a, const float* d_b, const float*
     hipStream_t s = static_cast<hipStream_t>(stream);
     int rc = prepare(rt, s);
     if (rc != AGILE_OK) return rc;
+    rc = trap_begin(rt, policy, s);
+    if (rc != AGILE_OK) return rc;
     const unsigned long long seq = rt->seq++;
     const Bind b[3] = {host_bind(rt, (uint64_t)d_b), host_bind(rt, (uint64_t)d_c),
                        host_bind(rt, (uint64_t)d_a)};
     if (launch_triad(true, rt->tab, rt->d_log, b, d_a, d_b, d_c, s_, n, seq,
-                     policy == AGILE_POLICY_SUPPRESS_LOG, rt->info, s) != hipSuccess)
+                     log_on(policy), rt->info, s) != hipSuccess)
         return AGILE_EDEVICE;
-    return AGILE_OK;
+    return trap_end(rt, policy, s);
 }
 
 static int rows_args_ok(uint64_t row_bytes, uint64_t n, int dtype, const void* a, const void* b,
@@ -589,6 +641,7 @@ static int rows_args_ok(uint64_t row_bytes, uint64_t n, int dtype, const void* a
 int agile_guarded_gather(agile_rt* rt, void* d_out, const void* d_table, uint64_t row_bytes,
                          const int64_t* d_idx, uint64_t n, int dtype, int policy, void* stream) {
     if (!rt || !policy_ok(policy)) return AGILE_EINVAL;
+    if (rt->retired) return AGILE_ETRAPPED;
     uint32_t w;
     int rc = rows_args_ok(row_bytes, n, dtype, d_out, d_table, &w);
     if (rc != AGILE_OK) return rc;
@@ -598,19 +651,22 @@ int agile_guarded_gather(agile_rt* rt, void* d_out, const void* d_table, uint64_
     hipStream_t s = static_cast<hipStream_t>(stream);
     rc = prepare(rt, s);
     if (rc != AGILE_OK) return rc;
+    rc = trap_begin(rt, policy, s);
+    if (rc != AGILE_OK) return rc;
     const unsigned long long seq = rt->seq++;
     const Bind b[3] = {host_bind(rt, (uint64_t)d_idx), host_bind(rt, (uint64_t)d_table),
                        host_bind(rt, (uint64_t)d_out)};
     if (launch_gather(true, rt->tab, rt->d_log, b, d_out, d_table, row_bytes, d_idx, n, w, seq,
-                      policy == AGILE_POLICY_SUPPRESS_LOG, rt->info, s) != hipSuccess)
+                      log_on(policy), rt->info, s) != hipSuccess)
         return AGILE_EDEVICE;
-    return AGILE_OK;
+    return trap_end(rt, policy, s);
 }
 
 int agile_guarded_scatter(agile_rt* rt, void* d_dst, uint64_t row_bytes, const int64_t* d_idx,
                           const void* d_src, uint64_t n, int dtype, int accumulate, int policy,
                           void* stream) {
     if (!rt || !policy_ok(policy) || (accumulate != 0 && accumulate != 1)) return AGILE_EINVAL;
+    if (rt->retired) return AGILE_ETRAPPED;
     uint32_t w;
     int rc = rows_args_ok(row_bytes, n, dtype, d_dst, d_src, &w);
     if (rc != AGILE_OK) return rc;
@@ -620,6 +676,8 @@ int agile_guarded_scatter(agile_rt* rt, void* d_dst, uint64_t row_bytes, const i
     hipStream_t s = static_cast<hipStream_t>(stream);
     rc = prepare(rt, s);
     if (rc != AGILE_OK) return rc;
+    rc = trap_begin(rt, policy, s);
+    if (rc != AGILE_OK) return rc;
     const unsigned long long seq = rt->seq++;
     const Bind b[3] = {host_bind(rt, (uint64_t)d_idx), host_bind(rt, (uint64_t)d_src),
                        host_bind(rt, (uint64_t)d_dst)};
@@ -627,9 +685,9 @@ int agile_guarded_scatter(agile_rt* rt, void* d_dst, uint64_t row_bytes, const i
                     ? grow_scratch(rt->sa_scratch, rt->sa_bytes, scatter_add_scratch_bytes(n))
                     : nullptr;
     if (launch_scatter(true, rt->tab, rt->d_log, b, d_dst, row_bytes, d_idx, d_src, n, w, accumulate,
-                       seq, policy == AGILE_POLICY_SUPPRESS_LOG, scr, rt->info, s) != hipSuccess)
+                       seq, log_on(policy), scr, rt->info, s) != hipSuccess)
         return AGILE_EDEVICE;
-    return AGILE_OK;
+    return trap_end(rt, policy, s);
 }
 
 int agile_fault_log_read(agile_rt* rt, agile_fault* out, int clear, void* stream) {
@@ -643,6 +701,7 @@ int agile_fault_log_read(agile_rt* rt, agile_fault* out, int clear, void* stream
         return AGILE_EDEVICE;
     *out = *rt->hlog;
     if (clear && launch_log_reset(rt->d_log, s) != hipSuccess) return AGILE_EDEVICE;
+    if (rt->retired) return AGILE_ETRAPPED;
     return out->count ? AGILE_EFAULTED : AGILE_OK;
 }
 
@@ -718,6 +777,7 @@ int agile_batch_run(agile_clients* cs, const agile_request* reqs, uint32_t nreq,
     for (uint32_t r = 0; r < nreq; ++r) {
         const agile_request& q = reqs[r];
         if (q.client >= ncl || q.ptr_off > nptrs || q.nptr > nptrs - q.ptr_off) return AGILE_EINVAL;
+        if (cs->tables[q.client]->retired) return AGILE_ETRAPPED;
         if (q.nptr > 0xFFFFFFFEull) return AGILE_EINVAL;
         if (q.gather_n && (q.gather_row_bytes == 0 || q.gather_row_bytes % 4 ||
                            ((q.gather_out | q.gather_table) & 3) || (q.gather_idx & 7) ||

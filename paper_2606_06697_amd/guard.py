@@ -19,9 +19,10 @@ LIB_PATH = os.path.join(_HERE, "libagile_guard.so")
 
 AGILE_OK, AGILE_EINVAL, AGILE_ENOMEM, AGILE_EOVERLAP = 0, -1, -2, -3
 AGILE_ENOENT, AGILE_ENOSPC, AGILE_EDEVICE, AGILE_EFAULTED = -4, -5, -6, -7
+AGILE_ETRAPPED = -8
 KIND_USER, KIND_PROTECTED, KIND_MMIO = 0, 1, 2
-ALLOW, V_PROTECTED, V_STRADDLE, V_UNMAPPED, V_CROSS_ALLOC = 0, 1, 2, 3, 4
-POLICY_SUPPRESS_LOG, POLICY_SUPPRESS_ONLY = 0, 1
+ALLOW, V_PROTECTED, V_STRADDLE, V_UNMAPPED, V_CROSS_ALLOC, V_INEXACT = 0, 1, 2, 3, 4, 5
+POLICY_SUPPRESS_LOG, POLICY_SUPPRESS_ONLY, POLICY_TRAP = 0, 1, 2
 OP_COPY, OP_TRIAD, OP_GATHER, OP_SCATTER, OP_SCATTER_ADD = 1, 2, 3, 4, 5
 DTYPE_F32, DTYPE_F64 = 0, 1
 NO_SEQ = (1 << 64) - 1
@@ -57,6 +58,7 @@ _SIGS = {
     "agile_rt_count": (_int, [_vp, ctypes.POINTER(_u32)]),
     "agile_rt_sync": (_int, [_vp, _vp]),
     "agile_validate_ptrs": (_int, [_vp, _vp, _u64, _vp, _vp, _vp]),
+    "agile_validate_dma": (_int, [_vp, _vp, _u64, _vp, _vp, _vp]),
     "agile_guarded_copy": (_int, [_vp, _vp, _vp, _u64, _int, _vp]),
     "agile_guarded_triad": (_int, [_vp, _vp, _vp, _vp, ctypes.c_float, _u64, _int, _vp]),
     "agile_guarded_gather": (_int, [_vp, _vp, _vp, _u64, _vp, _u64, _int, _int, _vp]),
@@ -181,6 +183,11 @@ def agile_validate_ptrs(rt: int, q, n: int, verdict, owner, stream=None) -> None
            "agile_validate_ptrs")
 
 
+def agile_validate_dma(rt: int, q, n: int, verdict, owner, stream=None) -> None:
+    _check(lib().agile_validate_dma(rt, _ptr(q), n, _ptr(verdict), _ptr(owner), _stream(stream)),
+           "agile_validate_dma")
+
+
 def agile_guarded_copy(rt: int, dst, src, nbytes: int, policy: int = 0, stream=None) -> None:
     _check(lib().agile_guarded_copy(rt, _ptr(dst), _ptr(src), nbytes, policy, _stream(stream)),
            "agile_guarded_copy")
@@ -205,11 +212,11 @@ def agile_guarded_scatter(rt: int, dst, row_bytes: int, idx, src, n: int, dtype:
 
 
 def agile_fault_log_read(rt: int, clear: bool = False, stream=None):
-    """Returns (status, record dict); status is AGILE_OK or AGILE_EFAULTED."""
+    """Returns (status, record dict); status is AGILE_OK, AGILE_EFAULTED or AGILE_ETRAPPED."""
     f = agile_fault()
     rc = _check(lib().agile_fault_log_read(rt, ctypes.byref(f), int(bool(clear)),
                                            _stream(stream)), "agile_fault_log_read",
-                ok=(AGILE_OK, AGILE_EFAULTED))
+                ok=(AGILE_OK, AGILE_EFAULTED, AGILE_ETRAPPED))
     return rc, f.as_dict()
 
 

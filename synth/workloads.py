@@ -181,6 +181,39 @@ def make_queries(table: Table, n: int, seed: int, device="cpu",
     return out
 
 
+def make_dma_queries(table: Table, n: int, seed: int, device="cpu") -> torch.Tensor:
+    """``n`` DMA registration queries [n, 2] = (addr, len): 40% the exact extent of a USER
+    range, 10% one byte short of it (from its base, or from base + 1), 5% one byte too long,
+    5% the exact extent of a protected range, 40% the pointer-query mix of ``make_queries``.
+    Categories are shuffled."""
+    g = _gen(seed, 9, device)
+    t = table.to(device)
+    base, size, kind = t.base, t.size, t.kind
+    user = torch.nonzero(kind == KIND_USER).flatten()
+    prot = torch.nonzero(kind != KIND_USER).flatten()
+    out = make_queries(table, n, seed, device).clone()
+    pick_n = lambda pool, m: pool[_uniform_below(torch.full((m,), pool.numel(), dtype=torch.int64,
+                                                            device=device), g)]
+    cut = torch.randperm(n, generator=g, device=device)
+    k0, k1, k2, k3 = (int(round(n * f)) for f in (0.40, 0.50, 0.55, 0.60))
+    if user.numel() and k1:
+        r = pick_n(user, k1)
+        a, L = base[r].clone(), size[r].clone()
+        short = torch.arange(k1, device=device) >= k0
+        from_next = short & (_uniform_below(torch.full((k1,), 2, dtype=torch.int64, device=device),
+                                            g) == 1) & (L > 1)
+        L = torch.where(short & (L > 1), L - 1, L)
+        a = torch.where(from_next, a + 1, a)
+        out[cut[:k1]] = torch.stack([a, L], 1)
+    if user.numel() and k2 > k1:
+        r = pick_n(user, k2 - k1)
+        out[cut[k1:k2]] = torch.stack([base[r], size[r] + 1], 1)
+    if prot.numel() and k3 > k2:
+        r = pick_n(prot, k3 - k2)
+        out[cut[k2:k3]] = torch.stack([base[r], size[r]], 1)
+    return out
+
+
 def uniform_f32(n: int, seed: int, device="cpu", stream: int = 3) -> torch.Tensor:
     """fp32 values uniform in [-1, 1)."""
     g = _gen(seed, stream, device)

@@ -52,12 +52,14 @@ def test_binding_covers_every_symbol():
 def test_argument_errors_fail_closed(L):
     from paper_2606_06697_amd import guard as g
     assert g.strerror(g.AGILE_EOVERLAP).startswith("range overlaps")
+    assert "trap policy" in g.strerror(g.AGILE_ETRAPPED)
     h = ctypes.c_void_p()
     assert L.agile_rt_create(ctypes.byref(h), 0, 0) == g.AGILE_EINVAL
     assert L.agile_rt_create(None, 16, 0) == g.AGILE_EINVAL
     assert L.agile_rt_insert(None, 0, 1, 0, None) == g.AGILE_EINVAL
     assert L.agile_rt_remove(None, 0) == g.AGILE_EINVAL
     assert L.agile_validate_ptrs(None, 0, 1, 0, 0, 0) == g.AGILE_EINVAL
+    assert L.agile_validate_dma(None, 0, 1, 0, 0, 0) == g.AGILE_EINVAL
     assert L.agile_guarded_copy(None, 0, 0, 16, 0, 0) == g.AGILE_EINVAL
     assert L.agile_guarded_gather(None, 0, 0, 4, 0, 1, 0, 0, 0) == g.AGILE_EINVAL
     assert L.agile_fault_log_read(None, None, 0, 0) == g.AGILE_EINVAL

@@ -412,3 +412,54 @@ def test_access_straddling_the_allocation_end_is_denied():
         assert log.count == 1
         assert (f["elem"], f["operand"], f["addr"], f["verdict"], f["owner"]) == \
             (2, 1, BASE + 9, V_STRADDLE, 0)
+
+
+# --- trap policy ----------------------------------------------------------------------
+def test_trap_policy_retires_on_a_violation_only():
+    """Reading of the paper's trap policy (Section V-E) with retirement of the worker whose
+    context can no longer be trusted (Section IV-D): a TRAP call without a denial is an
+    ordinary call; a violating TRAP call has exactly the suppress-and-log effect (the denied
+    access never happens), retires the handle and reports ETRAPPED; every later call of the
+    handle, under any policy, changes nothing and reports ETRAPPED; clearing the log does not
+    bring the handle back."""
+    t, mem, addr = scenario(4)
+    ref = copy.deepcopy(mem)
+    log, rlog = G.FaultLog(), G.FaultLog()
+    A, B, C, P = addr["A"], addr["B"], addr["C"], addr["P"]
+    assert G.guarded_call(G.copy_vec, t, mem, log, 0, C[0], A[0], 100, policy=G.TRAP) == G.OK
+    G.copy_vec(t, ref, rlog, 0, C[0], A[0], 100)
+    _same(mem, ref, addr)
+    assert not log.retired and log.count == 0
+    assert mem.read(C[0], 100) == mem.read(A[0], 100)
+    bad = (P[0] - A[0]) // 4 + 1                   # row inside the protected canary
+    for m in (mem, ref):
+        idx_ptr = _write_idx(m, addr, [3, bad, 5])
+    rc = G.guarded_call(G.gather_vec, t, mem, log, 1, C[0] + 200, A[0], 4, idx_ptr, 3,
+                        policy=G.TRAP)
+    G.gather_vec(t, ref, rlog, 1, C[0] + 200, A[0], 4, idx_ptr, 3)
+    assert rc == G.ETRAPPED and log.retired
+    _same(mem, ref, addr)
+    _logs_equal(log, rlog)
+    assert log.count == 1 and log.first["verdict"] == V_PROTECTED
+    assert mem.read(C[0] + 200, 12) == mem.read(A[0] + 12, 4) + bytes(4) + mem.read(A[0] + 20, 4)
+    # the calls below would change C if they ran
+    probe = copy.deepcopy(mem)
+    G.copy_vec(t, probe, G.FaultLog(), 2, C[0], B[0], 50)
+    assert probe.read(C[0], 50) != mem.read(C[0], 50)
+    snap = copy.deepcopy(mem)
+    for pol in (G.SUPPRESS_LOG, G.SUPPRESS_ONLY, G.TRAP):
+        assert G.guarded_call(G.copy_vec, t, mem, log, 2, C[0], B[0], 50, policy=pol) == G.ETRAPPED
+        assert G.guarded_call(G.triad_vec, t, mem, log, 3, C[0], B[0], C[0] + 64, 2.0, 16,
+                              policy=pol) == G.ETRAPPED
+        assert G.guarded_call(G.scatter_vec, t, mem, log, 4, C[0], 4, idx_ptr, B[0], 3, 4, True,
+                              policy=pol) == G.ETRAPPED
+    _same(mem, snap, addr)
+    _logs_equal(log, rlog)
+    log.clear()
+    assert log.retired and log.count == 0
+    # a violation under the other policies never retires
+    log2 = G.FaultLog()
+    for pol in (G.SUPPRESS_LOG, G.SUPPRESS_ONLY):
+        assert G.guarded_call(G.gather_vec, t, mem, log2, 5, C[0] + 200, A[0], 4, idx_ptr, 3,
+                              policy=pol) == G.OK
+    assert not log2.retired and log2.count == 1

@@ -3,18 +3,19 @@
 Each case plants one mistake in the oracle (monkeypatched for the duration of the test) and
 runs the pin tests that should notice it: the brute-force scan, the Table I fixture, the
 boundary invariants, the exact rational rounding of the triad, the loop-versus-vectorized
-agreement, the unit-gradient counts, the reason codes and the hand-derived straddling
-accesses. The unmodified oracle passes all of them; every planted mistake must make at least
+agreement, the unit-gradient counts, the reason codes, the hand-derived straddling
+accesses and the trap policy's retirement. The unmodified oracle passes all of them; every planted mistake must make at least
 one of them fail (an assertion, or an error such as reading memory outside an allocation).
 """
 import bisect
+import copy
 
 import numpy as np
 import pytest
 
 import oracle.guarded as G
-from oracle.table import (RangeTable, ALLOW, V_PROTECTED, V_STRADDLE, V_UNMAPPED, USER,
-                          PROTECTED)
+from oracle.table import (RangeTable, ALLOW, V_PROTECTED, V_STRADDLE, V_UNMAPPED, V_INEXACT,
+                          USER, PROTECTED)
 import test_oracle_guarded as PG
 import test_oracle_table as PT
 
@@ -28,13 +29,16 @@ def _fails(checks):
     return False
 
 
-TABLE_CHECKS = ([PT.test_table1_fixture, PT.test_boundary_invariants] +
-                [lambda s=s: PT.test_brute_force_exhaustive_boundaries(s) for s in range(12)])
+TABLE_CHECKS = ([PT.test_table1_fixture, PT.test_boundary_invariants,
+                 PT.test_dma_verdict_invariants] +
+                [lambda s=s: PT.test_brute_force_exhaustive_boundaries(s) for s in range(12)] +
+                [lambda s=s: PT.test_dma_verdict_brute_force(s) for s in range(8)])
 
 GUARD_CHECKS = ([PG.test_access_straddling_the_allocation_end_is_denied,
                  PG.test_triad_matches_exact_rational_rounding,
                  PG.test_scatter_add_unit_gradient_counts, PG.test_fault_reason_codes,
-                 PG.test_gather_no_fault_is_take, PG.test_copy_partial_closed_form_values] +
+                 PG.test_gather_no_fault_is_take, PG.test_copy_partial_closed_form_values,
+                 PG.test_trap_policy_retires_on_a_violation_only] +
                 [lambda s=s: PG.test_copy_vec_matches_loop(s) for s in range(6)] +
                 [lambda s=s: PG.test_triad_vec_matches_loop(s) for s in range(4)] +
                 [lambda s=s, w=w, D=D: PG.test_gather_vec_matches_loop(s, w, D)
@@ -75,6 +79,17 @@ def _owner_with(left=False, end_inclusive=False):
     return owner_entry
 
 
+def _dma_with(exact):
+    def dma_verdict(self, addr, length):
+        v, rid = self.verdict(addr, length)
+        if v == ALLOW:
+            b, end, _, _ = self.owner_entry(addr)
+            if not exact(int(addr), int(length), b, end):
+                v = V_INEXACT
+        return v, rid
+    return dma_verdict
+
+
 TABLE_MUTANTS = {
     "fit is strict (len < end - addr)": ("verdict", _verdict_with(fit=lambda L, room: L < room)),
     "fit off by one (len <= end - addr + 1)": ("verdict",
@@ -83,6 +98,10 @@ TABLE_MUTANTS = {
     "owner is the sorted position, not the id": ("verdict", _verdict_with(owner_pos=True)),
     "owner search finds the range ending at addr": ("owner_entry", _owner_with(left=True)),
     "range end counted as inside": ("owner_entry", _owner_with(end_inclusive=True)),
+    "DMA exactness ignores the length": ("dma_verdict", _dma_with(lambda a, L, b, e: a == b)),
+    "DMA exactness ignores the start": ("dma_verdict", _dma_with(lambda a, L, b, e: a + L == e)),
+    "DMA zero length taken as one byte": ("dma_verdict",
+                                          _dma_with(lambda a, L, b, e: a == b and max(L, 1) == e - b)),
 }
 
 
@@ -143,12 +162,47 @@ def _allowed_first_byte(bind, A, w):
     return bind[0] <= A < bind[1]
 
 
+def _trap_retires_every_call(orig):
+    def guarded_call(kernel, table, mem, log, seq, *args, policy=G.SUPPRESS_LOG, **kw):
+        if log.retired:
+            return G.ETRAPPED
+        kernel(table, mem, log, seq, *args, policy=policy, **kw)
+        if policy == G.TRAP:
+            log.retired = True
+            return G.ETRAPPED
+        return G.OK
+    return guarded_call
+
+
+def _retired_handle_keeps_running(orig):
+    def guarded_call(kernel, table, mem, log, seq, *args, policy=G.SUPPRESS_LOG, **kw):
+        was = log.retired
+        log.retired = False
+        rc = orig(kernel, table, mem, log, seq, *args, policy=policy, **kw)
+        log.retired = log.retired or was
+        return G.ETRAPPED if log.retired else rc
+    return guarded_call
+
+
+def _trapping_call_rolled_back(orig):
+    def guarded_call(kernel, table, mem, log, seq, *args, policy=G.SUPPRESS_LOG, **kw):
+        snap = copy.deepcopy(mem)
+        rc = orig(kernel, table, mem, log, seq, *args, policy=policy, **kw)
+        if rc == G.ETRAPPED:
+            mem.__dict__.update(snap.__dict__)
+        return rc
+    return guarded_call
+
+
 GUARD_MUTANTS = {
     "triad rounded once (fused)": ("triad_vec", _triad_one_rounding),
     "scatter-add overwrites": ("scatter_vec", _scatter_overwrites),
     "reason keeps ALLOW for cross-allocation": ("reason", lambda orig: _reason_without_remap),
     "access check excludes the last element": ("_allowed", lambda orig: _allowed_strict),
     "access check tests the first byte only": ("_allowed", lambda orig: _allowed_first_byte),
+    "trap retires the handle on a clean call": ("guarded_call", _trap_retires_every_call),
+    "retired handle keeps running its calls": ("guarded_call", _retired_handle_keeps_running),
+    "trapping call rolled back instead of suppressed": ("guarded_call", _trapping_call_rolled_back),
 }
 
 

@@ -10,8 +10,8 @@ import numpy as np
 import pytest
 
 from oracle import (RangeTable, OverlapError, ALLOW, V_PROTECTED, V_STRADDLE, V_UNMAPPED,
-                    USER, PROTECTED, MMIO, U64_MAX)
-from oracle.brute import verdict_brute
+                    V_INEXACT, USER, PROTECTED, MMIO, U64_MAX)
+from oracle.brute import verdict_brute, dma_verdict_brute
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -172,3 +172,49 @@ def test_generated_table_matches_brute_sample():
     counts = np.bincount(v, minlength=4)
     assert counts[ALLOW] > 2000 and counts[V_PROTECTED] > 500
     assert counts[V_STRADDLE] > 100 and counts[V_UNMAPPED] > 300
+
+
+# --- DMA registration: only an exact live user allocation (Section V-C) ---------------
+@pytest.mark.parametrize("seed", range(8))
+def test_dma_verdict_brute_force(seed):
+    """Against the definition (some USER entry equals [addr, addr+len) exactly), on every
+    boundary address and every length that reaches a boundary."""
+    rng = random.Random(100 + seed)
+    t = _random_table(rng, rng.randrange(1, 12), top=(seed % 4 == 3))
+    ents = t.entries()
+    A, L = [], []
+    for b, e, _, _ in ents:
+        for a in (b - 1, b, b + 1, e - 1):
+            if not 0 <= a <= U64_MAX:
+                continue
+            lens = {0, 1, 2, U64_MAX}
+            for b2, e2, _, _ in ents:
+                for x in (e2 - 1, e2, e2 + 1):
+                    if x >= a:
+                        lens.add(x - a)
+            for ln in sorted(lens):
+                assert t.dma_verdict(a, ln) == dma_verdict_brute(ents, a, ln), (a, ln)
+                A.append(a)
+                L.append(ln)
+    v, o = t.dma_verdict_many(np.array(A, np.uint64), np.array(L, np.uint64))
+    for k in range(len(A)):
+        assert (int(v[k]), int(o[k])) == t.dma_verdict(A[k], L[k])
+
+
+def test_dma_verdict_invariants():
+    t = RangeTable()
+    u = t.insert(1000, 100, USER)
+    p = t.insert(1100, 50, PROTECTED)
+    v = t.insert(1150, 1, USER)
+    assert t.dma_verdict(1000, 100) == (ALLOW, u)          # the whole allocation
+    assert t.dma_verdict(1000, 99) == (V_INEXACT, u)       # a prefix
+    assert t.dma_verdict(1001, 99) == (V_INEXACT, u)       # a suffix
+    assert t.dma_verdict(1010, 10) == (V_INEXACT, u)       # an interior piece
+    assert t.dma_verdict(1000, 0) == (V_INEXACT, u)        # zero length is never exact
+    assert t.dma_verdict(1000, 101) == (V_STRADDLE, u)     # one byte too long
+    assert t.dma_verdict(1100, 50) == (V_PROTECTED, p)     # exact, but protected
+    assert t.dma_verdict(1150, 1) == (ALLOW, v)            # one-byte allocation
+    assert t.dma_verdict(1150, 0) == (V_INEXACT, v)
+    assert t.dma_verdict(999, 101) == (V_UNMAPPED, -1)
+    t.remove(u)
+    assert t.dma_verdict(1000, 100) == (V_UNMAPPED, -1)    # freed: no longer live
