@@ -243,6 +243,8 @@ def main():
     if not args.no_extras:
         result["small_guard"] = bench_small_guard(g)
         result["table_build"] = bench_table_build(g, tb)
+        result["tokens"] = bench_tokens(g)
+        torch.cuda.empty_cache()
         result["embedding"] = bench_embedding(g, args)
         torch.cuda.empty_cache()
         result["batch"] = bench_batch(g, args)
@@ -387,6 +389,45 @@ def bench_table_build(g, tb):
             "single_inserts_per_s": round(m / (t1 - t0), 1),
             "single_removes_per_s": round((m // 4) / (t2 - t1), 1),
             "upload_after_edits_ms": round((t3 - t2) * 1e3, 3)}
+
+
+def bench_tokens(g):
+    """Client handle tokens: a 2^20-slot table with 2^19 live tokens of 64 clients (a third of
+    a further 2^18 released), and a batch of 2^26 presented tokens (live by their owner, by
+    other clients, released, bit-flipped), one device check per launch, 20 launches."""
+    import numpy as np
+    import torch
+
+    rng = np.random.default_rng(5)
+    cap, nlive, nrel, n = 1 << 20, 1 << 19, 1 << 18, 1 << 26
+    ts = g.TokenTable(cap, 0x5EED_0F_70CE_5)
+    owners = rng.integers(0, 64, nlive + nrel)
+    t0 = time.perf_counter()
+    toks = np.array([ts.mint(int(o), 0) for o in owners.tolist()], np.uint64)
+    mint_s = time.perf_counter() - t0
+    for i in range(nlive, nlive + nrel, 3):
+        ts.release(int(toks[i]), int(owners[i]))
+    dev = torch.device("cuda:0")
+    pick = torch.from_numpy(rng.integers(0, nlive + nrel, n)).to(dev)
+    tok = torch.from_numpy(toks.view(np.int64)).to(dev)[pick]
+    cli = torch.from_numpy(owners.astype(np.int32)).to(dev)[pick]
+    flip = torch.rand(n, device=dev) < 0.05
+    tok = torch.where(flip, tok ^ 1, tok)
+    other = torch.rand(n, device=dev) < 0.1
+    cli = torch.where(other, (cli + 1) % 64, cli)
+    v = torch.empty(n, dtype=torch.uint8, device=dev)
+    sl = torch.empty(n, dtype=torch.int32, device=dev)
+    ts_ = time_blocks({"check": lambda: g.agile_tokens_check(ts.handle, tok, cli, None, n, v, sl)},
+                      3, 20)
+    med = float(np.median(ts_["check"]))
+    counts = torch.bincount(v.long(), minlength=5).cpu().tolist()
+    ts.close()
+    return {"workload": "2^20 slots, 2^19 live tokens of 64 clients, 2^26 presented tokens",
+            "kernel_ms": round(med, 4),
+            "checks_per_s": round(n / (med / 1e3), 1),
+            "algorithmic_gbps": round(n * 17 / med / 1e6, 1),
+            "verdict_counts": counts,
+            "host_mints_per_s": round((nlive + nrel) / mint_s, 1)}
 
 
 def bench_embedding(g, args):

@@ -295,6 +295,47 @@ int agile_batch_run(agile_clients* cs, const agile_request* reqs, uint32_t nreq,
                     const agile_ptr* d_ptrs, uint64_t nptrs, uint8_t* d_ptr_verdict,
                     int32_t* d_ptr_owner, agile_req_result* d_result, void* stream);
 
+/* ---- client handle tokens (Section IV-C: client-visible objects are tokens backed by tables
+ * the worker owns, so fabricated, stale and cross-client handles are refused) --------------
+ * A token is 64 bits: slot << 40 | gen << 16 | tag. slot (24 bits) indexes the worker's slot
+ * table, gen (24 bits) is the slot's generation when the token was minted, and tag (16 bits)
+ * is the top 16 bits of SplitMix64(key ^ (slot << 24 | gen)) for the table's secret key
+ * (SplitMix64: Steele, Lea and Flood, 2014; state + 0x9e3779b97f4a7c15, then the published
+ * finalizer). Minting takes the lowest free slot; releasing advances the slot's generation,
+ * which makes every copy of the token stale; a slot released in its last generation is
+ * retired. */
+typedef struct agile_tokens agile_tokens; /* opaque, library-owned slot table */
+
+enum {
+    AGILE_TOKEN_VALID = 0,
+    AGILE_TOKEN_FORGED = 1,       /* never minted: bad slot, bad tag, or a generation not issued */
+    AGILE_TOKEN_STALE = 2,        /* minted, then released */
+    AGILE_TOKEN_CROSS_CLIENT = 3, /* live, but owned by another client */
+    AGILE_TOKEN_WRONG_KIND = 4    /* live and owned, but names another kind of object */
+};
+enum { AGILE_TOKEN_ANY_KIND = 255 };
+
+/* Create a table of `capacity` slots (1 <= capacity <= 2^24) on `device` with secret `key`.
+ * Errors: EINVAL, ENOMEM, EDEVICE. */
+int agile_tokens_create(agile_tokens** out, uint32_t capacity, uint64_t key, int device);
+/* Destroy (synchronizes the device first). NULL is accepted. */
+int agile_tokens_destroy(agile_tokens* ts);
+/* Mint a token for a new object of `kind` (0..254) owned by `client` (< 0xFFFFFFFE).
+ * Errors: EINVAL, ENOSPC (no free slot). */
+int agile_token_mint(agile_tokens* ts, uint32_t client, uint32_t kind, uint64_t* out_token);
+/* Release the object of a live token owned by `client`. Errors: EINVAL, ENOENT (the token is
+ * not a live token of this client; nothing changes). */
+int agile_token_release(agile_tokens* ts, uint64_t token, uint32_t client);
+/* Check n presented tokens in device memory: d_tokens[i] (uint64, 8-byte aligned) presented by
+ * client d_clients[i] (uint32), expecting kind d_kinds[i] (uint8, AGILE_TOKEN_ANY_KIND for any;
+ * d_kinds may be NULL: any kind). Writes d_verdict[i] (uint8, AGILE_TOKEN_*) and d_slot[i]
+ * (int32: the slot of a VALID token, else -1). Verdict order: FORGED, STALE, CROSS_CLIENT,
+ * WRONG_KIND, VALID. Mints and releases made before the call are seen by it (the slot records
+ * are refreshed in stream order). n == 0 is a no-op. Errors: EINVAL, EDEVICE. */
+int agile_tokens_check(agile_tokens* ts, const uint64_t* d_tokens, const uint32_t* d_clients,
+                       const uint8_t* d_kinds, uint64_t n, uint8_t* d_verdict, int32_t* d_slot,
+                       void* stream);
+
 /* Static text for a status code. */
 const char* agile_strerror(int code);
 

@@ -25,6 +25,8 @@ ALLOW, V_PROTECTED, V_STRADDLE, V_UNMAPPED, V_CROSS_ALLOC, V_INEXACT = 0, 1, 2, 
 POLICY_SUPPRESS_LOG, POLICY_SUPPRESS_ONLY, POLICY_TRAP = 0, 1, 2
 OP_COPY, OP_TRIAD, OP_GATHER, OP_SCATTER, OP_SCATTER_ADD = 1, 2, 3, 4, 5
 DTYPE_F32, DTYPE_F64 = 0, 1
+TOKEN_VALID, TOKEN_FORGED, TOKEN_STALE, TOKEN_CROSS_CLIENT, TOKEN_WRONG_KIND = 0, 1, 2, 3, 4
+TOKEN_ANY_KIND = 255
 NO_SEQ = (1 << 64) - 1
 
 
@@ -71,6 +73,11 @@ _SIGS = {
     "agile_clients_create": (_int, [ctypes.POINTER(_vp), _vp, _u32, _int]),
     "agile_clients_destroy": (_int, [_vp]),
     "agile_batch_run": (_int, [_vp, _vp, _u32, _vp, _u64, _vp, _vp, _vp, _vp]),
+    "agile_tokens_create": (_int, [ctypes.POINTER(_vp), _u32, _u64, _int]),
+    "agile_tokens_destroy": (_int, [_vp]),
+    "agile_token_mint": (_int, [_vp, _u32, _u32, ctypes.POINTER(_u64)]),
+    "agile_token_release": (_int, [_vp, _u64, _u32]),
+    "agile_tokens_check": (_int, [_vp, _vp, _vp, _vp, _u64, _vp, _vp, _vp]),
 }
 
 # numpy mirrors of agile_request (96 bytes) and agile_req_result (72 bytes)
@@ -269,6 +276,68 @@ def agile_batch_run(cs: int, reqs: np.ndarray, ptrs, nptrs: int, ptr_verdict, pt
 def batch_results(result: torch.Tensor, nreq: int) -> np.ndarray:
     """Copy a device result buffer to host as a RESULT_DTYPE array (synchronizes)."""
     return result[:nreq * RESULT_DTYPE.itemsize].cpu().numpy().view(RESULT_DTYPE).copy()
+
+
+def agile_tokens_create(capacity: int, key: int, device: int = 0) -> int:
+    h = _vp()
+    _check(lib().agile_tokens_create(ctypes.byref(h), capacity, key & ((1 << 64) - 1), device),
+           "agile_tokens_create")
+    return h.value
+
+
+def agile_tokens_destroy(ts: int) -> None:
+    _check(lib().agile_tokens_destroy(ts), "agile_tokens_destroy")
+
+
+def agile_token_mint(ts: int, client: int, kind: int) -> int:
+    out = _u64()
+    _check(lib().agile_token_mint(ts, client, kind, ctypes.byref(out)), "agile_token_mint")
+    return out.value
+
+
+def agile_token_release(ts: int, token: int, client: int) -> None:
+    _check(lib().agile_token_release(ts, token & ((1 << 64) - 1), client), "agile_token_release")
+
+
+def agile_tokens_check(ts: int, tokens, clients, kinds, n: int, verdict, slot,
+                       stream=None) -> None:
+    """tokens: device int64 [n] (bit patterns), clients: int32 [n], kinds: uint8 [n] or None,
+    verdict: uint8 [n], slot: int32 [n]."""
+    _check(lib().agile_tokens_check(ts, _ptr(tokens), _ptr(clients), _ptr(kinds), n,
+                                    _ptr(verdict), _ptr(slot), _stream(stream)),
+           "agile_tokens_check")
+
+
+class TokenTable:
+    """Owning wrapper of one token slot table."""
+
+    def __init__(self, capacity: int, key: int, device: int = 0):
+        self.handle = agile_tokens_create(capacity, key, device)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            agile_tokens_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def mint(self, client: int, kind: int) -> int:
+        return agile_token_mint(self.handle, client, kind)
+
+    def release(self, token: int, client: int) -> None:
+        agile_token_release(self.handle, token, client)
+
+    def check(self, tokens, clients, kinds=None, stream=None):
+        """Device tensors in, (verdict uint8, slot int32) device tensors out."""
+        n = tokens.numel()
+        v = torch.empty(n, dtype=torch.uint8, device=tokens.device)
+        s = torch.empty(n, dtype=torch.int32, device=tokens.device)
+        agile_tokens_check(self.handle, tokens, clients, kinds, n, v, s, stream)
+        return v, s
 
 
 class RangeTable:

@@ -60,6 +60,13 @@ def test_argument_errors_fail_closed(L):
     assert L.agile_rt_remove(None, 0) == g.AGILE_EINVAL
     assert L.agile_validate_ptrs(None, 0, 1, 0, 0, 0) == g.AGILE_EINVAL
     assert L.agile_validate_dma(None, 0, 1, 0, 0, 0) == g.AGILE_EINVAL
+    assert L.agile_tokens_create(None, 16, 1, 0) == g.AGILE_EINVAL
+    assert L.agile_tokens_create(ctypes.byref(h), 0, 1, 0) == g.AGILE_EINVAL
+    assert L.agile_tokens_create(ctypes.byref(h), (1 << 24) + 1, 1, 0) == g.AGILE_EINVAL
+    assert L.agile_token_mint(None, 0, 0, None) == g.AGILE_EINVAL
+    assert L.agile_token_release(None, 0, 0) == g.AGILE_EINVAL
+    assert L.agile_tokens_check(None, 0, 0, 0, 1, 0, 0, 0) == g.AGILE_EINVAL
+    assert L.agile_tokens_destroy(None) == g.AGILE_OK
     assert L.agile_guarded_copy(None, 0, 0, 16, 0, 0) == g.AGILE_EINVAL
     assert L.agile_guarded_gather(None, 0, 0, 4, 0, 1, 0, 0, 0) == g.AGILE_EINVAL
     assert L.agile_fault_log_read(None, None, 0, 0) == g.AGILE_EINVAL

@@ -4,7 +4,7 @@ Each case plants one mistake in the oracle (monkeypatched for the duration of th
 runs the pin tests that should notice it: the brute-force scan, the Table I fixture, the
 boundary invariants, the exact rational rounding of the triad, the loop-versus-vectorized
 agreement, the unit-gradient counts, the reason codes, the hand-derived straddling
-accesses and the trap policy's retirement. The unmodified oracle passes all of them; every planted mistake must make at least
+accesses, the trap policy's retirement and the handle tokens' history model. The unmodified oracle passes all of them; every planted mistake must make at least
 one of them fail (an assertion, or an error such as reading memory outside an allocation).
 """
 import bisect
@@ -14,10 +14,12 @@ import numpy as np
 import pytest
 
 import oracle.guarded as G
+import oracle.tokens as TK
 from oracle.table import (RangeTable, ALLOW, V_PROTECTED, V_STRADDLE, V_UNMAPPED, V_INEXACT,
                           USER, PROTECTED)
 import test_oracle_guarded as PG
 import test_oracle_table as PT
+import test_oracle_tokens as PK
 
 
 def _fails(checks):
@@ -211,3 +213,72 @@ def test_guard_mistake_is_caught(name, monkeypatch):
     attr, make = GUARD_MUTANTS[name]
     monkeypatch.setattr(G, attr, make(getattr(G, attr)))
     assert _fails(GUARD_CHECKS), name
+
+
+# ---- planted mistakes in the handle tokens -----------------------------------------------
+TOKEN_CHECKS = ([PK.test_splitmix64_published_outputs, PK.test_token_layout_and_slot_reuse_by_hand,
+                 PK.test_keys_separate_tables, PK.test_capacity_and_generation_retirement] +
+                [lambda s=s: PK.test_mechanism_matches_definition(s) for s in range(6)])
+
+
+def _check_with(stale_as_forged=False, skip_owner=False, skip_kind=False):
+    def check(self, token, client, want_kind=TK.ANY_KIND):
+        slot = token >> 40
+        gen = (token >> 16) & TK.GEN_MASK
+        if slot >= self.cap or (token & 0xFFFF) != TK.tag_of(self.key, slot, gen):
+            return TK.FORGED, -1
+        if gen < self.gen[slot] or self.retired[slot]:
+            return (TK.FORGED if stale_as_forged else TK.STALE), -1
+        if gen > self.gen[slot] or self.owner[slot] is None:
+            return TK.FORGED, -1
+        if not skip_owner and self.owner[slot] != client:
+            return TK.CROSS_CLIENT, -1
+        if not skip_kind and want_kind != TK.ANY_KIND and self.kind[slot] != want_kind:
+            return TK.WRONG_KIND, -1
+        return TK.VALID, slot
+    return check
+
+
+def _release_keeps_generation(self, token, client):
+    v, s = self.check(token, client)
+    if v != TK.VALID:
+        raise KeyError("not live")
+    self.owner[s] = None
+    import heapq
+    heapq.heappush(self.free, s)
+
+
+def _mint_highest_free(self, client, kind):
+    if self.free:
+        s = max(self.free)
+        self.free.remove(s)
+        import heapq
+        heapq.heapify(self.free)
+    elif self.next_new < self.cap:
+        s = self.next_new
+        self.next_new += 1
+    else:
+        raise MemoryError("full")
+    self.owner[s], self.kind[s] = client, kind
+    return TK.make_token(self.key, s, self.gen[s])
+
+
+TOKEN_MUTANTS = {
+    "stale token reported as forged": (TK.TokenTable, "check", _check_with(stale_as_forged=True)),
+    "owner not checked": (TK.TokenTable, "check", _check_with(skip_owner=True)),
+    "kind not checked": (TK.TokenTable, "check", _check_with(skip_kind=True)),
+    "release keeps the generation": (TK.TokenTable, "release", _release_keeps_generation),
+    "mint takes the highest free slot": (TK.TokenTable, "mint", _mint_highest_free),
+    "tag ignores the key": (TK, "tag_of", lambda key, slot, gen: TK.splitmix64((slot << 24) | gen) >> 48),
+}
+
+
+def test_unmodified_token_oracle_passes_every_pin():
+    assert not _fails(TOKEN_CHECKS)
+
+
+@pytest.mark.parametrize("name", sorted(TOKEN_MUTANTS))
+def test_token_mistake_is_caught(name, monkeypatch):
+    owner, attr, fn = TOKEN_MUTANTS[name]
+    monkeypatch.setattr(owner, attr, fn)
+    assert _fails(TOKEN_CHECKS), name
