@@ -20,7 +20,9 @@
  *    stream; the library never frees caller memory.
  *  - Streams: `stream` is a hipStream_t (NULL = the legacy default stream). Device work is
  *    queued asynchronously on it. Table mutations take effect for work queued after them
- *    (the device image is refreshed lazily, in stream order, by the next launch).
+ *    (the device image is refreshed lazily, in stream order, by the next launch; the handle
+ *    keeps two images, so a change does not wait for launches, on any stream, that still
+ *    read the previous table).
  *  - Threading: one handle must not be used from two host threads at once, and guarded
  *    calls on one handle that run concurrently on different streams race on its fault
  *    scratch; order them (one stream, or events).

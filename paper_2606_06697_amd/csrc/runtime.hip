@@ -42,6 +42,27 @@ struct DeviceGuard {
 constexpr uint32_t MAX_CAPACITY = 1u << 26;
 constexpr int32_t MAX_ID = (1 << 30) - 1;
 
+// One device copy of the table image (layout below) and its upload state.
+struct Image {
+    uint64_t* split64 = nullptr;
+    uint32_t* split32 = nullptr;
+    PairRec* rec = nullptr;
+    uint32_t* radix = nullptr;
+    uint4* nrec = nullptr;
+    void* stage = nullptr;           // pinned staging the upload copies from
+    hipEvent_t ready = nullptr;      // recorded after the upload into this image
+    hipStream_t ready_stream = nullptr;
+    bool uploaded = false;
+    // Recorded, when this image stopped being current, on every stream that had launched with
+    // it: the next upload into it waits for these (that is, for its last readers) only.
+    std::vector<hipEvent_t> retired;
+};
+
+void drop_events(std::vector<hipEvent_t>& v) {
+    for (hipEvent_t e : v) (void)hipEventDestroy(e);
+    v.clear();
+}
+
 }  // namespace
 
 struct agile_rt {
@@ -56,24 +77,18 @@ struct agile_rt {
     DevInfo info{};
     size_t lds_budget = 0;
     bool wide_only = false;  // never build narrow records (AGILE_WIDE_RECORDS=1)
-    // device image
+    // two device images with their pinned staging: a table change is built into the image that
+    // is not current, so launches still reading the current one are not waited for
     void* dmem = nullptr;
-    uint64_t* d_split64 = nullptr;
-    uint32_t* d_split32 = nullptr;
-    PairRec* d_rec = nullptr;
-    uint32_t* d_radix = nullptr;
-    uint4* d_nrec = nullptr;
+    Image img[2];
+    int cur = 0;
     DevLog* d_log = nullptr;
     DevTable tab{};
-    // pinned staging
-    void* hstage = nullptr;
     size_t stage_bytes = 0;
     agile_fault* hlog = nullptr;
     unsigned long long* htrap = nullptr;  // log count before / after a TRAP-policy call
     bool retired = false;                 // retired by a TRAP-policy violation
-    hipEvent_t upload_done = nullptr;
-    bool upload_pending = false;
-    std::vector<hipStream_t> streams_used;
+    std::vector<hipStream_t> streams_used;  // streams that launched with the current image
     // sort scratch of the scatter-add (grown on demand)
     void* sa_scratch = nullptr;
     size_t sa_bytes = 0;
@@ -218,16 +233,18 @@ static void note_stream(agile_rt* rt, hipStream_t s) {
     rt->streams_used.push_back(s);
 }
 
-// Build the image into the staging buffer and queue its upload on stream s.
+// Build the table into the image that is not current and queue its upload on stream s; that
+// image then becomes current. The upload waits on the device for the launches that read this
+// image while it was last current (two versions ago), not for those reading the current one.
 static int upload(agile_rt* rt, hipStream_t s) {
     if (!rt->dirty) return AGILE_OK;
-    if (rt->upload_pending) {
-        if (hipEventSynchronize(rt->upload_done) != hipSuccess) return AGILE_EDEVICE;
-        rt->upload_pending = false;
-    }
+    const int x = 1 - rt->cur;
+    Image& im = rt->img[x];
+    // the staging buffer may still feed this image's previous upload
+    if (im.uploaded && hipEventSynchronize(im.ready) != hipSuccess) return AGILE_EDEVICE;
     const uint32_t n = (uint32_t)rt->entries.size();
     const uint32_t nb = (n + 1) / 2;
-    uint8_t* h = static_cast<uint8_t*>(rt->hstage);
+    uint8_t* h = static_cast<uint8_t*>(im.stage);
     uint64_t* s64 = reinterpret_cast<uint64_t*>(h);
     uint32_t* s32 = reinterpret_cast<uint32_t*>(h + (size_t)rt->cap_nb * 8);
     PairRec* rec = reinterpret_cast<PairRec*>(h + rec_offset(rt->cap_nb));
@@ -253,10 +270,10 @@ static int upload(agile_rt* rt, hipStream_t s) {
         rec[b] = r;
     }
     DevTable t{};
-    t.split64 = rt->d_split64;
-    t.split32 = rt->d_split32;
-    t.rec = rt->d_rec;
-    t.radix = rt->d_radix;
+    t.split64 = im.split64;
+    t.split32 = im.split32;
+    t.rec = im.rec;
+    t.radix = im.radix;
     t.nb = nb;
     t.compressed = 0;
     if (nb > 0) {
@@ -275,46 +292,55 @@ static int upload(agile_rt* rt, hipStream_t s) {
         }
     }
     search_geometry(t, s64, radix, std::min(rt->lds_budget, rt->info.lds_per_block));
-    t.nrec = rt->d_nrec;
+    t.nrec = im.nrec;
     if (!rt->wide_only) build_narrow(t, s64, rec, nrec);
-    // make every other stream that used the handle finish with the old image first
+    // the last readers of image x
+    for (hipEvent_t e : im.retired)
+        if (hipStreamWaitEvent(s, e, 0) != hipSuccess) return AGILE_EDEVICE;
+    drop_events(im.retired);
+    // retire the current image: mark the end of every launch that reads it
+    Image& old = rt->img[rt->cur];
+    drop_events(old.retired);
     for (hipStream_t o : rt->streams_used) {
-        if (o == s) continue;
         hipEvent_t ev;
         if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return AGILE_EDEVICE;
-        if (hipEventRecord(ev, o) != hipSuccess || hipStreamWaitEvent(s, ev, 0) != hipSuccess) {
-            (void)hipEventDestroy(ev);
-            return AGILE_EDEVICE;
-        }
-        (void)hipEventDestroy(ev);
+        old.retired.push_back(ev);
+        if (hipEventRecord(ev, o) != hipSuccess) return AGILE_EDEVICE;
     }
     rt->streams_used.clear();
     if (nb > 0) {
-        if (hipMemcpyAsync(rt->d_split64, s64, (size_t)nb * 8, hipMemcpyHostToDevice, s) != hipSuccess)
+        if (hipMemcpyAsync(im.split64, s64, (size_t)nb * 8, hipMemcpyHostToDevice, s) != hipSuccess)
             return AGILE_EDEVICE;
         if (t.compressed &&
-            hipMemcpyAsync(rt->d_split32, s32, (size_t)nb * 4, hipMemcpyHostToDevice, s) != hipSuccess)
+            hipMemcpyAsync(im.split32, s32, (size_t)nb * 4, hipMemcpyHostToDevice, s) != hipSuccess)
             return AGILE_EDEVICE;
-        if (hipMemcpyAsync(rt->d_rec, rec, (size_t)nb * sizeof(PairRec), hipMemcpyHostToDevice, s) !=
+        if (hipMemcpyAsync(im.rec, rec, (size_t)nb * sizeof(PairRec), hipMemcpyHostToDevice, s) !=
             hipSuccess)
             return AGILE_EDEVICE;
     }
     if (t.narrow &&
-        hipMemcpyAsync(rt->d_nrec, nrec, (size_t)nb * 16, hipMemcpyHostToDevice, s) != hipSuccess)
+        hipMemcpyAsync(im.nrec, nrec, (size_t)nb * 16, hipMemcpyHostToDevice, s) != hipSuccess)
         return AGILE_EDEVICE;
-    if (hipMemcpyAsync(rt->d_radix, radix, (size_t)(t.nr + 1) * 4, hipMemcpyHostToDevice, s) !=
+    if (hipMemcpyAsync(im.radix, radix, (size_t)(t.nr + 1) * 4, hipMemcpyHostToDevice, s) !=
             hipSuccess ||
-        hipEventRecord(rt->upload_done, s) != hipSuccess)
+        hipEventRecord(im.ready, s) != hipSuccess)
         return AGILE_EDEVICE;
-    rt->upload_pending = true;
+    im.uploaded = true;
+    im.ready_stream = s;
+    rt->cur = x;
     rt->tab = t;
     rt->dirty = false;
     return AGILE_OK;
 }
 
+// Every launch with the table: bring the image up to date, and make sure a launch on another
+// stream than the one that uploaded the current image waits for that upload.
 static int prepare(agile_rt* rt, hipStream_t s) {
     int rc = upload(rt, s);
     if (rc != AGILE_OK) return rc;
+    const Image& im = rt->img[rt->cur];
+    if (im.uploaded && im.ready_stream != s && hipStreamWaitEvent(s, im.ready, 0) != hipSuccess)
+        return AGILE_EDEVICE;
     note_stream(rt, s);
     return AGILE_OK;
 }
@@ -363,24 +389,32 @@ int agile_rt_create(agile_rt** out, uint32_t capacity, int device) {
     }
     if (const char* e = std::getenv("AGILE_WIDE_RECORDS")) rt->wide_only = std::atoi(e) != 0;
     rt->stage_bytes = image_bytes(rt->cap_nb);
-    const size_t dev_bytes = rt->stage_bytes + 256 + sizeof(DevLog);
+    const size_t img_bytes = ((rt->stage_bytes + 255) / 256) * 256;
+    const size_t dev_bytes = 2 * img_bytes + sizeof(DevLog);
     if (hipMalloc(&rt->dmem, dev_bytes) != hipSuccess) {
         delete rt;
         return AGILE_ENOMEM;
     }
-    uint8_t* d = static_cast<uint8_t*>(rt->dmem);
-    rt->d_split64 = reinterpret_cast<uint64_t*>(d);
-    rt->d_split32 = reinterpret_cast<uint32_t*>(d + (size_t)rt->cap_nb * 8);
-    rt->d_rec = reinterpret_cast<PairRec*>(d + rec_offset(rt->cap_nb));
-    rt->d_radix = reinterpret_cast<uint32_t*>(d + radix_offset(rt->cap_nb));
-    rt->d_nrec = reinterpret_cast<uint4*>(d + nrec_offset(rt->cap_nb));
-    rt->d_log = reinterpret_cast<DevLog*>(d + ((rt->stage_bytes + 255) / 256) * 256);
-    if (hipHostMalloc(&rt->hstage, rt->stage_bytes, hipHostMallocDefault) != hipSuccess ||
+    for (int k = 0; k < 2; ++k) {
+        uint8_t* d = static_cast<uint8_t*>(rt->dmem) + k * img_bytes;
+        Image& im = rt->img[k];
+        im.split64 = reinterpret_cast<uint64_t*>(d);
+        im.split32 = reinterpret_cast<uint32_t*>(d + (size_t)rt->cap_nb * 8);
+        im.rec = reinterpret_cast<PairRec*>(d + rec_offset(rt->cap_nb));
+        im.radix = reinterpret_cast<uint32_t*>(d + radix_offset(rt->cap_nb));
+        im.nrec = reinterpret_cast<uint4*>(d + nrec_offset(rt->cap_nb));
+        if (hipHostMalloc(&im.stage, rt->stage_bytes, hipHostMallocDefault) != hipSuccess ||
+            hipEventCreateWithFlags(&im.ready, hipEventDisableTiming) != hipSuccess) {
+            agile_rt_destroy(rt);
+            return AGILE_ENOMEM;
+        }
+    }
+    rt->d_log = reinterpret_cast<DevLog*>(static_cast<uint8_t*>(rt->dmem) + 2 * img_bytes);
+    if (
         hipHostMalloc(reinterpret_cast<void**>(&rt->hlog), sizeof(agile_fault),
                       hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&rt->htrap), 2 * sizeof(unsigned long long),
-                      hipHostMallocDefault) != hipSuccess ||
-        hipEventCreateWithFlags(&rt->upload_done, hipEventDisableTiming) != hipSuccess) {
+                      hipHostMallocDefault) != hipSuccess) {
         agile_rt_destroy(rt);
         return AGILE_ENOMEM;
     }
@@ -398,8 +432,11 @@ int agile_rt_destroy(agile_rt* rt) {
     DeviceGuard dg(rt->device);
     int rc = AGILE_OK;
     if (hipDeviceSynchronize() != hipSuccess) rc = AGILE_EDEVICE;
-    if (rt->upload_done) (void)hipEventDestroy(rt->upload_done);
-    if (rt->hstage) (void)hipHostFree(rt->hstage);
+    for (Image& im : rt->img) {
+        if (im.ready) (void)hipEventDestroy(im.ready);
+        if (im.stage) (void)hipHostFree(im.stage);
+        drop_events(im.retired);
+    }
     if (rt->hlog) (void)hipHostFree(rt->hlog);
     if (rt->htrap) (void)hipHostFree(rt->htrap);
     if (rt->dmem) (void)hipFree(rt->dmem);
