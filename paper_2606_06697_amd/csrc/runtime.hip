@@ -53,6 +53,7 @@ struct Image {
     hipEvent_t ready = nullptr;      // recorded after the upload into this image
     hipStream_t ready_stream = nullptr;
     bool uploaded = false;
+    bool ready_done = false;         // the upload is known to have completed
     // Recorded, when this image stopped being current, on every stream that had launched with
     // it: the next upload into it waits for these (that is, for its last readers) only.
     std::vector<hipEvent_t> retired;
@@ -326,6 +327,7 @@ static int upload(agile_rt* rt, hipStream_t s) {
         hipEventRecord(im.ready, s) != hipSuccess)
         return AGILE_EDEVICE;
     im.uploaded = true;
+    im.ready_done = false;
     im.ready_stream = s;
     rt->cur = x;
     rt->tab = t;
@@ -338,9 +340,15 @@ static int upload(agile_rt* rt, hipStream_t s) {
 static int prepare(agile_rt* rt, hipStream_t s) {
     int rc = upload(rt, s);
     if (rc != AGILE_OK) return rc;
-    const Image& im = rt->img[rt->cur];
-    if (im.uploaded && im.ready_stream != s && hipStreamWaitEvent(s, im.ready, 0) != hipSuccess)
-        return AGILE_EDEVICE;
+    Image& im = rt->img[rt->cur];
+    if (im.uploaded && !im.ready_done && im.ready_stream != s) {
+        const hipError_t q = hipEventQuery(im.ready);
+        if (q == hipSuccess) {
+            im.ready_done = true;
+        } else if (q != hipErrorNotReady || hipStreamWaitEvent(s, im.ready, 0) != hipSuccess) {
+            return AGILE_EDEVICE;
+        }
+    }
     note_stream(rt, s);
     return AGILE_OK;
 }
