@@ -22,38 +22,26 @@
 
 #include "agile_guard.h"
 
-namespace {
+namespace agile {
 
 constexpr uint32_t SLOT_MAX = 1u << 24;
 constexpr uint32_t GEN_MASK = (1u << 24) - 1;
 constexpr uint32_t OWNER_FREE = 0xFFFFFFFFu, OWNER_RETIRED = 0xFFFFFFFEu;
 constexpr int TBLOCK = 256, TPT = 4;  // tokens per thread per pass
 
-__host__ __device__ inline uint64_t splitmix64(uint64_t x) {
+static __host__ __device__ inline uint64_t splitmix64(uint64_t x) {
     uint64_t z = x + 0x9E3779B97F4A7C15ull;
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     return z ^ (z >> 31);
 }
 
-__host__ __device__ inline uint32_t token_tag(uint64_t key, uint32_t slot, uint32_t gen) {
+static __host__ __device__ inline uint32_t token_tag(uint64_t key, uint32_t slot, uint32_t gen) {
     return (uint32_t)(splitmix64(key ^ (((uint64_t)slot << 24) | gen)) >> 48);
 }
 
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = false;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) return;
-        ok = prev == dev || hipSetDevice(dev) == hipSuccess;
-    }
-    ~DeviceGuard() {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
-
 // One verdict; `rec` is the slot's record (read only when the slot is in range).
-__device__ __forceinline__ uint8_t judge(uint64_t tok, uint32_t slot, uint2 rec, uint64_t key,
+static __device__ __forceinline__ uint8_t judge(uint64_t tok, uint32_t slot, uint2 rec, uint64_t key,
                                          uint32_t client, uint32_t want) {
     const uint32_t gen = (uint32_t)(tok >> 16) & GEN_MASK;
     if ((uint32_t)(tok & 0xFFFFu) != token_tag(key, slot, gen)) return AGILE_TOKEN_FORGED;
@@ -100,7 +88,29 @@ __global__ __launch_bounds__(TBLOCK) void k_tokens_check(
     }
 }
 
+}  // namespace agile
+
+namespace {
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) return;
+        ok = prev == dev || hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
 }  // namespace
+
+using agile::GEN_MASK;
+using agile::OWNER_FREE;
+using agile::OWNER_RETIRED;
+using agile::SLOT_MAX;
+using agile::TBLOCK;
+using agile::TPT;
+using agile::token_tag;
 
 struct agile_tokens {
     int device = 0;
@@ -273,7 +283,7 @@ int agile_tokens_check(agile_tokens* ts, const uint64_t* d_tokens, const uint32_
     uint64_t grid = (n + per_block - 1) / per_block;
     const uint64_t cap = (uint64_t)ts->num_cu * 8;
     if (grid > cap) grid = cap;
-    hipLaunchKernelGGL(k_tokens_check, dim3((uint32_t)grid), dim3(TBLOCK), 0, s, ts->d_rec,
+    hipLaunchKernelGGL(agile::k_tokens_check, dim3((uint32_t)grid), dim3(TBLOCK), 0, s, ts->d_rec,
                        ts->cap, ts->key, d_tokens, d_clients, d_kinds, n, d_verdict, d_slot);
     return hipGetLastError() == hipSuccess ? AGILE_OK : AGILE_EDEVICE;
 }
