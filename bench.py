@@ -574,8 +574,8 @@ def bench_serving(g, args):
 
 
 def cpu_baseline(tb, step_bytes, nq):
-    """Time the oracle (as it stands) on a bounded sample of the same workload, single thread,
-    and scale each part to its full size."""
+    """Time the oracle (as it stands) on a bounded sample of the same workload (about 10 s of
+    single-thread CPU work) and scale each part to its full size."""
     import numpy as np
     import torch
 
@@ -587,13 +587,13 @@ def cpu_baseline(tb, step_bytes, nq):
     ot = OT()
     for bb, s, k in zip(tb.base.tolist(), tb.size.tolist(), tb.kind.tolist()):
         ot.insert(bb, s, k)
-    nsv = 1 << 23
+    nsv = 1 << 26
     qs = make_queries(tb, nsv, SEED + 100).numpy().view(np.uint64)
     t0 = time.perf_counter()
     ot.verdict_many(qs[:, 0], qs[:, 1])
     tv = time.perf_counter() - t0
 
-    nst = 1 << 22
+    nst = 1 << 25
     base = 1 << 40
     mt, tt = Memory(), OT()
     for k, arr in enumerate((np.zeros(nst, np.float32), uniform_f32(nst, 5).numpy(),
@@ -604,7 +604,7 @@ def cpu_baseline(tb, step_bytes, nq):
     G.triad_vec(tt, mt, G.FaultLog(), 0, base, base + (1 << 30), base + (2 << 30), 3.0, nst)
     ttr = time.perf_counter() - t0
 
-    nsg, rows = 1 << 18, 1 << 22
+    nsg, rows = 1 << 21, 1 << 24
     mg, tg = Memory(), OT()
     idx = uniform_indices(nsg, rows, 7, bad_frac=0.001,
                           bad_ranges=((rows, rows + 16384), (rows + 16384, rows + 32768))).numpy()
