@@ -14,7 +14,11 @@ serves many clients from one process:
   the global HBM budget for in-flight outputs, and a launch slot (stream) is free;
 * every poll retires finished launches (their event completed: latencies are recorded, output
   space is returned) and launches the admitted requests as one persistent batch on a free
-  stream, so new work overlaps the batches already on the device.
+  stream, so new work overlaps the batches already on the device;
+* revocation (Section IV-D, lifetime and revocation: a client's resources are revoked when its
+  assignment ends): at a given time every range of the client's table is removed while other
+  batches are still on the device, and its requests from then on are refused without a launch.
+  Launches made before keep the table they were made with (the library's two table images).
 
 Latency = completion seen by the loop minus arrival, on the host clock.
 """
@@ -85,7 +89,7 @@ class _Ring:
             self.live.popitem(last=False)
             self.tail = k + n
         if not self.live:
-            self.tail = self.head
+            self.head = self.tail = 0     # empty: start over at the ring's base
 
 
 @dataclass
@@ -107,13 +111,13 @@ class Server:
         self.dev = torch.device(device)
         gen = _gen(cfg.seed, 20)
         nr = loguniform_int(cfg.ranges[0], cfg.ranges[1], cfg.n_clients, gen).tolist()
-        self.tables, self.rings = [], []
+        self.tables, self.rings, self.range_ids, self.synth_tables = [], [], [], []
         self.gtab, self.gidx, self.csrc, self.ring_mem = [], [], [], []
         ptr_chunks = []
         for c in range(cfg.n_clients):
             tb = make_table(nr[c], max(1, nr[c] // 8), cfg.seed * 1000 + c, first_hi=2**44)
             rt = g.RangeTable(nr[c] + 16)
-            rt.insert_many(tb.base, tb.size, tb.kind)
+            ids = rt.insert_many(tb.base, tb.size, tb.kind).tolist()
             gt = torch.rand(cfg.gather_table_bytes // 4, device=self.dev)
             rows = gt.numel()
             idx = torch.randint(0, rows, (cfg.idx_pool,), device=self.dev)
@@ -124,8 +128,10 @@ class Server:
             src = torch.randint(0, 256, (cfg.copy_src_bytes,), dtype=torch.uint8, device=self.dev)
             ring = torch.empty(cfg.ring_bytes, dtype=torch.uint8, device=self.dev)
             for t in (gt, idx, src, ring):
-                rt.insert_tensor(t, g.KIND_USER)
+                ids.append(rt.insert_tensor(t, g.KIND_USER))
             self.tables.append(rt)
+            self.range_ids.append(ids)
+            self.synth_tables.append(tb)
             self.gtab.append(gt)
             self.gidx.append(idx)
             self.csrc.append(src)
@@ -137,6 +143,7 @@ class Server:
         self.pv = torch.empty(self.nptrs, dtype=torch.uint8, device=self.dev)
         self.po = torch.empty(self.nptrs, dtype=torch.int32, device=self.dev)
         self.cs = g.agile_clients_create(self.tables, self.dev.index or 0)
+        self.revoked_at = {}
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(cfg.max_inflight)]
         self.results = [torch.empty(cfg.max_batch * g.RESULT_DTYPE.itemsize, dtype=torch.uint8,
                                     device=self.dev) for _ in range(cfg.max_inflight)]
@@ -150,6 +157,15 @@ class Server:
         for rt in self.tables:
             rt.close()
         self.tables = []
+
+    def revoke(self, client, when=0.0):
+        """End a client's assignment: remove every range of its table (later launches see an
+        empty table) and refuse its requests from now on."""
+        rt = self.tables[client]
+        for rid in self.range_ids[client]:
+            rt.remove(rid)
+        self.range_ids[client] = []
+        self.revoked_at[client] = when
 
     # ------------------------------------------------------------------ requests
     def make_requests(self, trace):
@@ -184,16 +200,22 @@ class Server:
         return reqs, out_bytes
 
     # ------------------------------------------------------------------ the loop
-    def run(self, trace, record=None):
+    def run(self, trace, record=None, revoke=None):
         """Serve a trace; returns latencies (s) per request, completion order and stats.
 
         record: optional set of request ids whose results and outputs are copied to host at
-        completion (for identity checks)."""
+        completion (for identity checks). revoke: optional {client: time in s}; the client is
+        revoked at the first poll at or after that trace time. Afterwards ``self.t_launch``
+        holds each request's launch time (NaN if refused) and ``self.refused`` which requests
+        were refused."""
         cfg = self.cfg
         reqs, out_bytes = self.make_requests(trace)
         arr = trace["t"].numpy()
         n = arr.size
         lat = np.full(n, np.nan)
+        t_launch = np.full(n, np.nan)
+        refused = np.zeros(n, dtype=bool)
+        due = sorted((t, c) for c, t in (revoke or {}).items())
         kept = {}
         pending = collections.deque()
         inflight = []
@@ -222,6 +244,9 @@ class Server:
                 else:
                     still.append(b)
             inflight = still
+            # revocations that are due, while other batches may still be on the device
+            while due and due[0][0] <= now:
+                self.revoke(due.pop(0)[1], now)
             # arrivals
             while nxt < n and arr[nxt] <= now:
                 pending.append(nxt)
@@ -231,6 +256,11 @@ class Server:
                 take, allocs, nbytes = [], [], 0
                 while pending and len(take) < cfg.max_batch:
                     r = pending[0]
+                    if int(reqs["client"][r]) in self.revoked_at:
+                        pending.popleft()
+                        refused[r] = True
+                        done += 1
+                        continue
                     need = int(out_bytes[r])
                     if inflight_bytes + nbytes + need > cfg.hbm_budget:
                         break
@@ -256,6 +286,7 @@ class Server:
                                       self.results[slot], stream=st)
                     ev = torch.cuda.Event()
                     ev.record(st)
+                    t_launch[rids] = now
                     inflight.append(_Inflight(ev, rids, allocs, nbytes, slot, batch))
                     inflight_bytes += nbytes
                     launches += 1
@@ -277,7 +308,9 @@ class Server:
             "launches": launches,
             "mean_batch": float(ok.sum() / max(launches, 1)),
             "moved_gb_per_s": moved / elapsed / 1e9,
+            "refused": int(refused.sum()),
         }
+        self.t_launch, self.refused = t_launch, refused
         return lat, stats, kept
 
     def _record(self, b, record, kept):
