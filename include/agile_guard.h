@@ -157,6 +157,11 @@ int agile_rt_insert_many(agile_rt* rt, const uint64_t* base, const uint64_t* siz
  * Errors: EINVAL, ENOENT. */
 int agile_rt_remove(agile_rt* rt, int32_t id);
 
+/* Remove every range: the end of a client's assignment revokes all of its allocations
+ * (Section IV-D, lifetime and revocation). Ids are not reused afterwards. Launches queued
+ * before the call keep the table they were queued with. Works on a retired handle. */
+int agile_rt_clear(agile_rt* rt);
+
 /* Number of live ranges. */
 int agile_rt_count(const agile_rt* rt, uint32_t* out_n);
 
@@ -337,6 +342,58 @@ int agile_token_release(agile_tokens* ts, uint64_t token, uint32_t client);
 int agile_tokens_check(agile_tokens* ts, const uint64_t* d_tokens, const uint32_t* d_clients,
                        const uint8_t* d_kinds, uint64_t n, uint8_t* d_verdict, int32_t* d_slot,
                        void* stream);
+
+/* ---- native serving loop (Section IV-B: a worker executes its clients' mediated requests;
+ * Sections IV-C, IV-E: each pointer argument is checked against the calling client's table
+ * first; Section IV-D: revocation when a client's assignment ends) -----------------------
+ * Open-loop continuous batching over agile_batch_run: requests arrive at given times, wait in
+ * a FIFO, are admitted while their output fits the client's output ring and the in-flight HBM
+ * budget, and run as persistent batches on up to max_inflight streams, so new batches overlap
+ * the ones still on the device. */
+typedef struct agile_server agile_server; /* opaque */
+
+typedef struct {
+    uint32_t max_batch;     /* requests per launch, 1..65536 */
+    uint32_t max_inflight;  /* launches on the device at once (one stream each), 1..16 */
+    uint64_t hbm_budget;    /* bytes of outputs in flight, all clients together */
+} agile_server_config;
+
+enum { AGILE_SERVER_MAX_REVOKE = 16 };
+
+typedef struct {
+    double elapsed_s;
+    uint64_t launches;
+    uint64_t served;
+    uint64_t refused;       /* revoked client, or an output larger than its ring or the budget */
+    double revoked_at_s[AGILE_SERVER_MAX_REVOKE]; /* when each revocation took effect */
+} agile_server_stats;
+
+/* A server for client set cs (whose client i is tables[i]), with client i's output ring at
+ * device address ring_base[i] (256-byte aligned) of ring_bytes[i] bytes (registered in its
+ * table by the caller). d_ptrs / d_ptr_verdict / d_ptr_owner: the pointer pool and its outputs,
+ * as in agile_batch_run. Everything stays owned by the caller. Errors: EINVAL, ENOMEM. */
+int agile_server_create(agile_server** out, agile_clients* cs, agile_rt* const* tables,
+                        uint32_t nclients, const uint64_t* ring_base, const uint64_t* ring_bytes,
+                        const agile_server_config* cfg, const agile_ptr* d_ptrs, uint64_t nptrs,
+                        uint8_t* d_ptr_verdict, int32_t* d_ptr_owner, int device);
+int agile_server_destroy(agile_server* sv);
+
+/* Serve n requests (host arrays). reqs[i] arrives arrival_s[i] seconds after the call starts
+ * (non-decreasing); its output slice (out_bytes[i] bytes, 0 for validation) is taken from its
+ * client's ring and written into reqs[i].copy_dst or gather_out (reqs is in/out). Client
+ * revoke_client[k] is revoked (agile_rt_clear) at revoke_s[k]: launches made before keep the
+ * table they were made with, and its requests from then on are refused. Outputs per request:
+ * latency_s (completion seen by the loop minus arrival, NaN if refused), launch_s (NaN if
+ * refused), results (may be NULL: agile_req_result per request). record (may be NULL): for
+ * requests with record[i] != 0, at completion the output bytes and then, for validation, the
+ * nptr verdict bytes and nptr owner int32s are copied to rec_buf + rec_off[i]. Returns when
+ * every request completed or was refused. Errors: EINVAL, EDEVICE, or those of
+ * agile_batch_run. */
+int agile_server_run(agile_server* sv, agile_request* reqs, const uint64_t* out_bytes,
+                     const double* arrival_s, uint64_t n, const uint32_t* revoke_client,
+                     const double* revoke_s, uint32_t nrevoke, const uint8_t* record,
+                     uint8_t* rec_buf, const uint64_t* rec_off, double* latency_s,
+                     double* launch_s, agile_req_result* results, agile_server_stats* stats);
 
 /* Static text for a status code. */
 const char* agile_strerror(int code);

@@ -529,6 +529,14 @@ int agile_rt_remove(agile_rt* rt, int32_t id) {
     return AGILE_OK;
 }
 
+int agile_rt_clear(agile_rt* rt) {
+    if (!rt) return AGILE_EINVAL;
+    rt->entries.clear();
+    rt->by_id.clear();
+    rt->dirty = true;
+    return AGILE_OK;
+}
+
 int agile_rt_count(const agile_rt* rt, uint32_t* out_n) {
     if (!rt || !out_n) return AGILE_EINVAL;
     *out_n = (uint32_t)rt->entries.size();
@@ -752,7 +760,7 @@ int agile_fault_log_read(agile_rt* rt, agile_fault* out, int clear, void* stream
 
 // ---- batched multi-client requests -----------------------------------------------------
 namespace {
-constexpr int BATCH_SLOTS = 4;
+constexpr int BATCH_SLOTS = 8;
 struct BatchSlot {
     void* dmem = nullptr;
     size_t dcap = 0;
@@ -846,8 +854,26 @@ int agile_batch_run(agile_clients* cs, const agile_request* reqs, uint32_t nreq,
     const size_t o_gd = o_tb + align64((size_t)ncl * sizeof(DevTable));
     const size_t o_tr = o_gd + align64((size_t)nreq * sizeof(BatchGuard));
     const size_t bytes = o_tr + align64((size_t)ntiles * 4);
-    BatchSlot& sl = cs->slot[cs->next];
-    cs->next = (cs->next + 1) % BATCH_SLOTS;
+    // a staging slot whose last launch has finished (launches complete out of order), else the
+    // next one in turn, waited for
+    int pick = -1;
+    for (int k = 0; k < BATCH_SLOTS && pick < 0; ++k) {
+        const int j = (cs->next + k) % BATCH_SLOTS;
+        if (!cs->slot[j].used) {
+            pick = j;
+        } else {
+            const hipError_t q = hipEventQuery(cs->slot[j].done);
+            if (q == hipSuccess) {
+                cs->slot[j].used = false;
+                pick = j;
+            } else if (q != hipErrorNotReady) {
+                return AGILE_EDEVICE;
+            }
+        }
+    }
+    if (pick < 0) pick = cs->next;
+    BatchSlot& sl = cs->slot[pick];
+    cs->next = (pick + 1) % BATCH_SLOTS;
     if (sl.used) {
         if (hipEventSynchronize(sl.done) != hipSuccess) return AGILE_EDEVICE;
         sl.used = false;

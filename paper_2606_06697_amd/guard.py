@@ -50,6 +50,19 @@ class agile_fault(ctypes.Structure):
 
 _u64, _u32, _i32, _int, _vp = (ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_int,
                                ctypes.c_void_p)
+SERVER_MAX_REVOKE = 16
+
+
+class agile_server_config(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_uint32), ("max_inflight", ctypes.c_uint32),
+                ("hbm_budget", ctypes.c_uint64)]
+
+
+class agile_server_stats(ctypes.Structure):
+    _fields_ = [("elapsed_s", ctypes.c_double), ("launches", ctypes.c_uint64),
+                ("served", ctypes.c_uint64), ("refused", ctypes.c_uint64),
+                ("revoked_at_s", ctypes.c_double * SERVER_MAX_REVOKE)]
+
 _SIGS = {
     "agile_strerror": (ctypes.c_char_p, [_int]),
     "agile_rt_create": (_int, [ctypes.POINTER(_vp), _u32, _int]),
@@ -78,6 +91,13 @@ _SIGS = {
     "agile_token_mint": (_int, [_vp, _u32, _u32, ctypes.POINTER(_u64)]),
     "agile_token_release": (_int, [_vp, _u64, _u32]),
     "agile_tokens_check": (_int, [_vp, _vp, _vp, _vp, _u64, _vp, _vp, _vp]),
+    "agile_rt_clear": (_int, [_vp]),
+    "agile_server_create": (_int, [ctypes.POINTER(_vp), _vp, _vp, _u32, _vp, _vp,
+                                   ctypes.POINTER(agile_server_config), _vp, _u64, _vp, _vp,
+                                   _int]),
+    "agile_server_destroy": (_int, [_vp]),
+    "agile_server_run": (_int, [_vp, _vp, _vp, _vp, _u64, _vp, _vp, _u32, _vp, _vp, _vp, _vp,
+                                _vp, _vp, ctypes.POINTER(agile_server_stats)]),
 }
 
 # numpy mirrors of agile_request (96 bytes) and agile_req_result (72 bytes)
@@ -276,6 +296,58 @@ def agile_batch_run(cs: int, reqs: np.ndarray, ptrs, nptrs: int, ptr_verdict, pt
 def batch_results(result: torch.Tensor, nreq: int) -> np.ndarray:
     """Copy a device result buffer to host as a RESULT_DTYPE array (synchronizes)."""
     return result[:nreq * RESULT_DTYPE.itemsize].cpu().numpy().view(RESULT_DTYPE).copy()
+
+
+def agile_rt_clear(rt: int) -> None:
+    _check(lib().agile_rt_clear(rt), "agile_rt_clear")
+
+
+def agile_server_create(cs: int, tables, ring_base, ring_bytes, max_batch: int,
+                        max_inflight: int, hbm_budget: int, ptrs, nptrs: int, ptr_verdict,
+                        ptr_owner, device: int = 0) -> int:
+    """tables: table handles (ints) or RangeTable objects, client i = tables[i];
+    ring_base / ring_bytes: per-client output rings (device addresses, bytes)."""
+    hs = [t.handle if isinstance(t, RangeTable) else int(t) for t in tables]
+    arr = (_vp * len(hs))(*hs)
+    rb = np.ascontiguousarray(ring_base, dtype=np.uint64)
+    rs = np.ascontiguousarray(ring_bytes, dtype=np.uint64)
+    cfg = agile_server_config(max_batch, max_inflight, hbm_budget)
+    h = _vp()
+    _check(lib().agile_server_create(ctypes.byref(h), cs, arr, len(hs), rb.ctypes.data,
+                                     rs.ctypes.data, ctypes.byref(cfg), _ptr(ptrs), nptrs,
+                                     _ptr(ptr_verdict), _ptr(ptr_owner), device),
+           "agile_server_create")
+    return h.value
+
+
+def agile_server_destroy(sv: int) -> None:
+    _check(lib().agile_server_destroy(sv), "agile_server_destroy")
+
+
+def agile_server_run(sv: int, reqs: np.ndarray, out_bytes, arrival_s, revoke_client=None,
+                     revoke_s=None, record=None, rec_buf=None, rec_off=None):
+    """reqs: REQUEST_DTYPE array (in/out: output addresses are filled in). Returns
+    (latency_s, launch_s, results, stats) as numpy arrays and an agile_server_stats."""
+    assert reqs.dtype == REQUEST_DTYPE and reqs.flags.c_contiguous
+    n = len(reqs)
+    ob = np.ascontiguousarray(out_bytes, dtype=np.uint64)
+    ar = np.ascontiguousarray(arrival_s, dtype=np.float64)
+    rc_ = np.ascontiguousarray(revoke_client if revoke_client is not None else [], np.uint32)
+    rt_ = np.ascontiguousarray(revoke_s if revoke_s is not None else [], np.float64)
+    lat = np.empty(n, np.float64)
+    lau = np.empty(n, np.float64)
+    res = np.zeros(n, RESULT_DTYPE)
+    st = agile_server_stats()
+    rec = None if record is None else np.ascontiguousarray(record, np.uint8)
+    roff = None if rec_off is None else np.ascontiguousarray(rec_off, np.uint64)
+    _check(lib().agile_server_run(sv, reqs.ctypes.data, ob.ctypes.data, ar.ctypes.data, n,
+                                  rc_.ctypes.data, rt_.ctypes.data, len(rc_),
+                                  None if rec is None else rec.ctypes.data,
+                                  None if rec_buf is None else rec_buf.ctypes.data,
+                                  None if roff is None else roff.ctypes.data,
+                                  lat.ctypes.data, lau.ctypes.data, res.ctypes.data,
+                                  ctypes.byref(st)), "agile_server_run")
+    return lat, lau, res, st
 
 
 def agile_tokens_create(capacity: int, key: int, device: int = 0) -> int:
