@@ -294,8 +294,9 @@ int agile_clients_destroy(agile_clients* cs);
 
 /* Run `nreq` requests (host array) in one persistent launch on `stream`. d_ptrs holds the
  * pointer arguments of all requests (device, 16-byte aligned); d_ptr_verdict / d_ptr_owner
- * (device, one entry per pointer) receive each pointer's verdict and owner; d_result (device,
- * nreq entries) receives each request's result. The request array is copied before the call
+ * (device, one entry per pointer) receive each pointer's verdict and owner; d_result (device
+ * memory, or pinned host memory from hipHostMalloc; nreq entries) receives each request's
+ * result. The request array is copied before the call
  * returns. Requests must not write into each other's inputs or outputs. Errors: EINVAL (bad
  * client index, sizes, alignment), ENOMEM, EDEVICE. */
 int agile_batch_run(agile_clients* cs, const agile_request* reqs, uint32_t nreq,

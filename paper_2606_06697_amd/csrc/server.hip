@@ -5,7 +5,8 @@
 // Host code only; every request runs in the persistent batch kernel through agile_batch_run.
 // The loop polls, in order:
 //  1. retire: launches whose completion event has fired give their requests' latencies and
-//     results (copied to pinned memory on the launch's stream) and return their output space;
+//     results (written by the batch kernel straight into pinned host memory) and return their
+//     output space;
 //  2. revoke: clients whose assignment ends now lose every range (agile_rt_clear); launches
 //     already queued keep the table they were made with;
 //  3. arrive: requests whose arrival time has passed join a FIFO;
@@ -44,8 +45,8 @@ struct DeviceGuard {
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    void* d_res = nullptr;       // agile_req_result[max_batch], device
-    void* h_res = nullptr;       // pinned copy
+    void* h_res = nullptr;       // agile_req_result[max_batch], pinned host memory that the
+                                 // batch kernel writes directly (read after its event fires)
     bool busy = false;
     std::vector<uint64_t> rids;
     std::vector<std::pair<uint32_t, uint64_t>> allocs;  // (client, ring start)
@@ -100,7 +101,6 @@ int agile_server_create(agile_server** out, agile_clients* cs, agile_rt* const* 
     for (Slot& sl : sv->slots) {
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
-            hipMalloc(&sl.d_res, rbytes) != hipSuccess ||
             hipHostMalloc(&sl.h_res, rbytes, hipHostMallocDefault) != hipSuccess) {
             agile_server_destroy(sv);
             return AGILE_ENOMEM;
@@ -117,7 +117,6 @@ int agile_server_destroy(agile_server* sv) {
     for (Slot& sl : sv->slots) {
         if (sl.stream && hipStreamSynchronize(sl.stream) != hipSuccess) rc = AGILE_EDEVICE;
         if (sl.done) (void)hipEventDestroy(sl.done);
-        if (sl.d_res) (void)hipFree(sl.d_res);
         if (sl.h_res) (void)hipHostFree(sl.h_res);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
     }
@@ -257,12 +256,9 @@ int agile_server_run(agile_server* sv, agile_request* reqs, const uint64_t* out_
             if (!batch.empty()) {
                 int rc = agile_batch_run(sv->cs, batch.data(), (uint32_t)batch.size(), sv->d_ptrs,
                                          sv->nptrs, sv->d_pv, sv->d_po,
-                                         static_cast<agile_req_result*>(sl.d_res), sl.stream);
+                                         static_cast<agile_req_result*>(sl.h_res), sl.stream);
                 if (rc != AGILE_OK) return rc;
-                if (hipMemcpyAsync(sl.h_res, sl.d_res, batch.size() * sizeof(agile_req_result),
-                                   hipMemcpyDeviceToHost, sl.stream) != hipSuccess ||
-                    hipEventRecord(sl.done, sl.stream) != hipSuccess)
-                    return AGILE_EDEVICE;
+                if (hipEventRecord(sl.done, sl.stream) != hipSuccess) return AGILE_EDEVICE;
                 for (uint64_t r : sl.rids) launch_s[r] = now;
                 sl.nbytes = nbytes;
                 inflight_bytes += nbytes;
