@@ -14,21 +14,33 @@ namespace agile {
 
 constexpr int BBLOCK = 256;
 constexpr uint64_t TILE_PTRS = 2048;       // pointers per validation tile (8 per thread)
-constexpr uint64_t TILE_COPY = 2ull << 20; // bytes per copy tile
+constexpr uint64_t TILE_COPY_MAX = 2ull << 20;  // bytes per copy tile, large launches
 constexpr int COPY_U = 8;                 // 16-byte vectors in flight per thread
 constexpr uint64_t COPY_CHUNK = (uint64_t)BBLOCK * COPY_U * 16;  // one pass of a workgroup
-constexpr uint64_t TILE_ROWS = 16384;      // rows per gather tile
+constexpr uint64_t TILE_ROWS_MAX = 16384;  // rows per gather tile, large launches
+constexpr uint64_t TILE_ROWS_MIN = 512;
 constexpr int VQ = 8;
+constexpr uint32_t LDS_SPLIT = 4096;       // bucket splitters staged in LDS for the search
 
-__device__ inline void tiles_of(const BatchReq& q, uint64_t& vt, uint64_t& ct) {
+__device__ inline void tiles_of(const BatchReq& q, uint64_t tile_copy, uint64_t& vt,
+                                uint64_t& ct) {
     vt = (q.nptr + TILE_PTRS - 1) / TILE_PTRS;
-    ct = (q.copy_bytes + TILE_COPY - 1) / TILE_COPY;
+    ct = (q.copy_bytes + tile_copy - 1) / tile_copy;
 }
 
 // VQ pointer queries per lane, searched together (uniform trip count over the client table).
+// Tables of up to LDS_SPLIT buckets have their splitters staged in LDS first (one round of
+// coalesced loads instead of a chain of dependent global loads per query); larger ones are
+// searched in global memory (L2-resident).
 __device__ inline void validate_tile(const DevTable& t, const ulonglong2* ptrs, uint64_t p0,
                                      uint64_t k0, uint64_t k1, uint8_t* pv, int32_t* po,
-                                     uint32_t& minfail) {
+                                     uint32_t& minfail, uint64_t* s_split) {
+    const bool staged = t.nb <= LDS_SPLIT;
+    if (staged) {
+        for (uint32_t k = threadIdx.x; k < t.nb; k += BBLOCK) s_split[k] = t.split64[k];
+        __syncthreads();
+    }
+    const uint64_t* sp = staged ? s_split : t.split64;
     uint64_t a[VQ], L[VQ];
     uint32_t base[VQ];
     bool live[VQ];
@@ -44,8 +56,7 @@ __device__ inline void validate_tile(const DevTable& t, const ulonglong2* ptrs, 
     for (uint32_t len = t.nb; len > 1;) {
         const uint32_t half = len >> 1;
 #pragma unroll
-        for (int q = 0; q < VQ; ++q)
-            base[q] = t.split64[base[q] + half] <= a[q] ? base[q] + half : base[q];
+        for (int q = 0; q < VQ; ++q) base[q] = sp[base[q] + half] <= a[q] ? base[q] + half : base[q];
         len -= half;
     }
 #pragma unroll
@@ -54,7 +65,7 @@ __device__ inline void validate_tile(const DevTable& t, const ulonglong2* ptrs, 
         const uint64_t k = k0 + (uint64_t)q * BBLOCK + threadIdx.x;
         uint8_t v = V_UNMAPPED;
         int32_t o = -1;
-        if (t.nb > 0 && t.split64[base[q]] <= a[q]) classify_in_bucket(load_rec(t.rec + base[q]), a[q], L[q], v, o);
+        if (t.nb > 0 && sp[base[q]] <= a[q]) classify_in_bucket(load_rec(t.rec + base[q]), a[q], L[q], v, o);
         pv[p0 + k] = v;
         po[p0 + k] = o;
         if (v != V_ALLOW && (uint32_t)k < minfail) minfail = (uint32_t)k;
@@ -229,6 +240,7 @@ __device__ inline void finish_request(const BatchArgs& A, uint32_t r) {
 __global__ __launch_bounds__(BBLOCK) void k_batch(BatchArgs A) {
     __shared__ uint32_t s_tile, s_next;
     __shared__ uint32_t s_minfail;
+    __shared__ uint64_t s_split[LDS_SPLIT];
     const uint32_t tid = threadIdx.x;
     if (tid == 0) s_next = atomicAdd(&A.ctl->next, 1u);
     while (true) {
@@ -247,13 +259,13 @@ __global__ __launch_bounds__(BBLOCK) void k_batch(BatchArgs A) {
         const BatchReq q = A.reqs[r];
         const DevTable& t = A.tables[q.client];
         uint64_t vt, ct;
-        tiles_of(q, vt, ct);
+        tiles_of(q, A.tile_copy, vt, ct);
         const uint64_t local = tile - A.tstart[r];
         if (local < vt) {
             const uint64_t k0 = local * TILE_PTRS;
             const uint64_t k1 = k0 + TILE_PTRS < q.nptr ? k0 + TILE_PTRS : q.nptr;
             uint32_t mf = 0xFFFFFFFFu;
-            validate_tile(t, A.ptrs, q.ptr_off, k0, k1, A.pv, A.po, mf);
+            validate_tile(t, A.ptrs, q.ptr_off, k0, k1, A.pv, A.po, mf, s_split);
             atomicMin(&s_minfail, mf);
             __syncthreads();
             if (tid == 0 && s_minfail != 0xFFFFFFFFu) atomicMin(&A.scratch[r].minfail, s_minfail);
@@ -268,8 +280,8 @@ __global__ __launch_bounds__(BBLOCK) void k_batch(BatchArgs A) {
                           A.guards[r].copy_ks, A.guards[r].copy_kd);
             }
         } else if (q.gather_n) {
-            const uint64_t i0 = (local - vt - ct) * TILE_ROWS;
-            const uint64_t i1 = i0 + TILE_ROWS < q.gather_n ? i0 + TILE_ROWS : q.gather_n;
+            const uint64_t i0 = (local - vt - ct) * A.tile_rows;
+            const uint64_t i1 = i0 + A.tile_rows < q.gather_n ? i0 + A.tile_rows : q.gather_n;
             FaultAcc acc;
             gather_tile(q, A.guards[r].gather, i0, i1, acc);
             const unsigned long long c = wave_sum_u64(acc.cnt);
@@ -298,10 +310,21 @@ hipError_t launch_batch(const BatchArgs& A, const DevInfo& d, hipStream_t s) {
     return hipGetLastError();
 }
 
-uint64_t batch_tiles(const BatchReq& q) {
+void batch_tile_sizes(uint64_t copy_bytes, uint64_t gather_rows, const DevInfo& d,
+                      uint64_t& tile_copy, uint64_t& tile_rows) {
+    // about two tiles per CU for each kind of work, within [one workgroup pass, the maximum]
+    const uint64_t want = 2ull * (uint64_t)(d.num_cu > 0 ? d.num_cu : 1);
+    uint64_t tc = copy_bytes / want;
+    tc = (tc + COPY_CHUNK - 1) / COPY_CHUNK * COPY_CHUNK;
+    tile_copy = tc < COPY_CHUNK ? COPY_CHUNK : (tc > TILE_COPY_MAX ? TILE_COPY_MAX : tc);
+    uint64_t tr = gather_rows / want;
+    tile_rows = tr < TILE_ROWS_MIN ? TILE_ROWS_MIN : (tr > TILE_ROWS_MAX ? TILE_ROWS_MAX : tr);
+}
+
+uint64_t batch_tiles(const BatchReq& q, uint64_t tile_copy, uint64_t tile_rows) {
     const uint64_t vt = (q.nptr + TILE_PTRS - 1) / TILE_PTRS;
-    const uint64_t ct = (q.copy_bytes + TILE_COPY - 1) / TILE_COPY;
-    const uint64_t gt = (q.gather_n + TILE_ROWS - 1) / TILE_ROWS;
+    const uint64_t ct = (q.copy_bytes + tile_copy - 1) / tile_copy;
+    const uint64_t gt = (q.gather_n + tile_rows - 1) / tile_rows;
     const uint64_t all = vt + ct + gt;
     return all ? all : 1;
 }

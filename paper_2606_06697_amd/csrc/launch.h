@@ -121,11 +121,17 @@ struct BatchArgs {
     int32_t* po;
     agile_req_result_dev* result;
     uint64_t ntiles;
+    uint64_t tile_copy;  // bytes per copy tile of this launch
+    uint64_t tile_rows;  // rows per gather tile of this launch
     uint32_t nreq;
     uint32_t pad;
 };
 
-uint64_t batch_tiles(const BatchReq& q);
+// Tile sizes of one launch: small launches get small tiles, so that even one request spreads
+// over the whole chip; large launches get the largest tiles (fewer claims, longer streams).
+void batch_tile_sizes(uint64_t copy_bytes, uint64_t gather_rows, const DevInfo& d,
+                      uint64_t& tile_copy, uint64_t& tile_rows);
+uint64_t batch_tiles(const BatchReq& q, uint64_t tile_copy, uint64_t tile_rows);
 hipError_t launch_batch(const BatchArgs& a, const DevInfo& d, hipStream_t s);
 
 }  // namespace agile

@@ -826,7 +826,7 @@ int agile_batch_run(agile_clients* cs, const agile_request* reqs, uint32_t nreq,
     if (nptrs && (!d_ptrs || !d_ptr_verdict || !d_ptr_owner || ((uint64_t)d_ptrs & 15)))
         return AGILE_EINVAL;
     const uint32_t ncl = (uint32_t)cs->tables.size();
-    uint64_t ntiles = 0;
+    uint64_t total_copy = 0, total_rows = 0;
     for (uint32_t r = 0; r < nreq; ++r) {
         const agile_request& q = reqs[r];
         if (q.client >= ncl || q.ptr_off > nptrs || q.nptr > nptrs - q.ptr_off) return AGILE_EINVAL;
@@ -836,8 +836,14 @@ int agile_batch_run(agile_clients* cs, const agile_request* reqs, uint32_t nreq,
                            ((q.gather_out | q.gather_table) & 3) || (q.gather_idx & 7) ||
                            q.gather_n > ((1ull << 62) - 1) / (q.gather_row_bytes / 4)))
             return AGILE_EINVAL;
-        ntiles += batch_tiles(reinterpret_cast<const BatchReq&>(q));
+        total_copy = q.copy_bytes > U64MAX - total_copy ? U64MAX : total_copy + q.copy_bytes;
+        total_rows = q.gather_n > U64MAX - total_rows ? U64MAX : total_rows + q.gather_n;
     }
+    uint64_t tile_copy, tile_rows;
+    batch_tile_sizes(total_copy, total_rows, cs->tables[0]->info, tile_copy, tile_rows);
+    uint64_t ntiles = 0;
+    for (uint32_t r = 0; r < nreq; ++r)
+        ntiles += batch_tiles(reinterpret_cast<const BatchReq&>(reqs[r]), tile_copy, tile_rows);
     DeviceGuard dg(cs->device);
     if (!dg.ok) return AGILE_EDEVICE;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -854,26 +860,27 @@ int agile_batch_run(agile_clients* cs, const agile_request* reqs, uint32_t nreq,
     const size_t o_gd = o_tb + align64((size_t)ncl * sizeof(DevTable));
     const size_t o_tr = o_gd + align64((size_t)nreq * sizeof(BatchGuard));
     const size_t bytes = o_tr + align64((size_t)ntiles * 4);
-    // a staging slot whose last launch has finished (launches complete out of order), else the
+    // a staging slot whose last launch has finished (launches complete out of order): the
+    // first one already large enough, else the first free one (it grows); with none free, the
     // next one in turn, waited for
-    int pick = -1;
-    for (int k = 0; k < BATCH_SLOTS && pick < 0; ++k) {
-        const int j = (cs->next + k) % BATCH_SLOTS;
-        if (!cs->slot[j].used) {
-            pick = j;
-        } else {
-            const hipError_t q = hipEventQuery(cs->slot[j].done);
-            if (q == hipSuccess) {
-                cs->slot[j].used = false;
-                pick = j;
-            } else if (q != hipErrorNotReady) {
-                return AGILE_EDEVICE;
-            }
+    int fit = -1, any = -1;
+    for (int j = 0; j < BATCH_SLOTS && fit < 0; ++j) {
+        BatchSlot& c = cs->slot[j];
+        if (c.used) {
+            const hipError_t q = hipEventQuery(c.done);
+            if (q == hipErrorNotReady) continue;
+            if (q != hipSuccess) return AGILE_EDEVICE;
+            c.used = false;
         }
+        if (c.dcap >= bytes) fit = j;
+        else if (any < 0) any = j;
     }
-    if (pick < 0) pick = cs->next;
+    int pick = fit >= 0 ? fit : any;
+    if (pick < 0) {
+        pick = cs->next;
+        cs->next = (cs->next + 1) % BATCH_SLOTS;
+    }
     BatchSlot& sl = cs->slot[pick];
-    cs->next = (pick + 1) % BATCH_SLOTS;
     if (sl.used) {
         if (hipEventSynchronize(sl.done) != hipSuccess) return AGILE_EDEVICE;
         sl.used = false;
@@ -903,7 +910,7 @@ int agile_batch_run(agile_clients* cs, const agile_request* reqs, uint32_t nreq,
     uint64_t acc = 0;
     for (uint32_t r = 0; r < nreq; ++r) {
         std::memcpy(&rq[r], &reqs[r], sizeof(BatchReq));
-        const uint64_t k = batch_tiles(rq[r]);
+        const uint64_t k = batch_tiles(rq[r], tile_copy, tile_rows);
         for (uint64_t j = 0; j < k; ++j) tr[acc + j] = r;
         ts[r] = acc;
         acc += k;
@@ -941,6 +948,8 @@ int agile_batch_run(agile_clients* cs, const agile_request* reqs, uint32_t nreq,
     A.po = d_ptr_owner;
     A.result = reinterpret_cast<agile_req_result_dev*>(d_result);
     A.ntiles = ntiles;
+    A.tile_copy = tile_copy;
+    A.tile_rows = tile_rows;
     A.nreq = nreq;
     if (launch_batch(A, cs->tables[0]->info, s) != hipSuccess) return AGILE_EDEVICE;
     if (hipEventRecord(sl.done, s) != hipSuccess) return AGILE_EDEVICE;
