@@ -69,8 +69,9 @@ __global__ __launch_bounds__(TBLOCK) void k_tokens_check(
         for (int j = 0; j < TPT; ++j) {
             const uint64_t i = i0 + (uint64_t)j * nth;
             const bool in = i < n;
-            t[j] = in ? tok[i] : 0;
-            c[j] = in ? cli[i] : 0;
+            // streamed once: non-temporal, so they do not push the slot records out of L2
+            t[j] = in ? __builtin_nontemporal_load(tok + i) : 0;
+            c[j] = in ? __builtin_nontemporal_load(cli + i) : 0;
             w[j] = (in && kinds) ? kinds[i] : AGILE_TOKEN_ANY_KIND;
             s[j] = (uint32_t)(t[j] >> 40);
         }
@@ -82,8 +83,8 @@ __global__ __launch_bounds__(TBLOCK) void k_tokens_check(
             if (i >= n) break;
             const uint8_t v = s[j] < cap ? judge(t[j], s[j], r[j], key, c[j], w[j])
                                          : (uint8_t)AGILE_TOKEN_FORGED;
-            verdict[i] = v;
-            slot_out[i] = v == AGILE_TOKEN_VALID ? (int32_t)s[j] : -1;
+            __builtin_nontemporal_store(v, verdict + i);
+            __builtin_nontemporal_store(v == AGILE_TOKEN_VALID ? (int32_t)s[j] : -1, slot_out + i);
         }
     }
 }
