@@ -235,8 +235,8 @@ __device__ __forceinline__ void chunk_packed(const DevTable& t, const unsigned c
                 owner[i] = o;
             }
         } else {
-            vp[j * 64] = v;
-            op[j * 64] = o;
+            __builtin_nontemporal_store(v, vp + j * 64);  // written once, not read back
+            __builtin_nontemporal_store(o, op + j * 64);
         }
     }
 }
