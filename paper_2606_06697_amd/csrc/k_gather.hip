@@ -61,7 +61,9 @@ __device__ __forceinline__ void load_rows(const RowLanes& L, uint64_t r0, uint64
 #pragma unroll
     for (int u = 0; u < R; ++u) {
         const uint64_t i = r0 + u * L.rpw + L.riw;
-        int64_t x = i < nfast ? idx[i] : 0;
+        // narrow rows: each index is read once, non-temporally (kept out of L2 and the MALL,
+        // which then hold more table lines); wide rows read one index per wave
+        int64_t x = i < nfast ? (WIDE ? idx[i] : __builtin_nontemporal_load(idx + i)) : 0;
         if (WIDE) x = (int64_t)uniform_u64((uint64_t)x);
         iv[u] = x;
     }
