@@ -401,7 +401,9 @@ struct RowVec {
     typename FloatOf<W>::F v[EPL];
 };
 
-template <int W, int EPL>
+// NT: a row read once (a source row of the sum): non-temporal, so it does not push the
+// destination rows, which are read, summed and written back, out of the caches.
+template <int W, int EPL, bool NT = false>
 __device__ __forceinline__ RowVec<W, EPL> load_row(const uint8_t* src, uint64_t rb, uint32_t row,
                                                    uint64_t col0) {
     using F = typename FloatOf<W>::F;
@@ -409,14 +411,15 @@ __device__ __forceinline__ RowVec<W, EPL> load_row(const uint8_t* src, uint64_t 
     const F* sp = reinterpret_cast<const F*>(src + (uint64_t)row * rb) + col0;
     if (EPL == 4) {
         typedef F f4 __attribute__((ext_vector_type(4)));
-        const f4 v = *reinterpret_cast<const f4*>(sp);
+        const f4* vp = reinterpret_cast<const f4*>(sp);
+        const f4 v = NT ? __builtin_nontemporal_load(vp) : *vp;
         r.v[0] = v.x;
         r.v[EPL > 1 ? 1 : 0] = v.y;
         r.v[EPL > 2 ? 2 : 0] = v.z;
         r.v[EPL > 3 ? 3 : 0] = v.w;
     } else {
 #pragma unroll
-        for (int q = 0; q < EPL; ++q) r.v[q] = sp[q];
+        for (int q = 0; q < EPL; ++q) r.v[q] = NT ? __builtin_nontemporal_load(sp + q) : sp[q];
     }
     return r;
 }
@@ -508,7 +511,7 @@ __global__ __launch_bounds__(256) void k_srt_reduce(uint8_t* dst, uint64_t rb,
 #pragma unroll
                     for (int u = 0; u < RED_U; ++u) {
                         if (kk[u] != SRT_SENT && on) {
-                            rv[u] = load_row<W, EPL>(src, rb, vv[u], col0);
+                            rv[u] = load_row<W, EPL, true>(src, rb, vv[u], col0);
                             const uint32_t prev = u == 0 ? cur : kk[u - 1];
                             if (kk[u] != prev)
                                 dv[u] = load_row<W, EPL>(dst + (uint64_t)(base + (int64_t)kk[u]) * rb,
