@@ -14,6 +14,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "device_guard.h"
 #include "agile_guard.h"
 #include "launch.h"
 
@@ -27,17 +28,7 @@ struct Entry {
     uint8_t kind;
 };
 
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = false;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) return;
-        ok = prev == dev || hipSetDevice(dev) == hipSuccess;
-    }
-    ~DeviceGuard() {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
+using agile::DeviceGuard;
 
 constexpr uint32_t MAX_CAPACITY = 1u << 26;
 constexpr int32_t MAX_ID = (1 << 30) - 1;

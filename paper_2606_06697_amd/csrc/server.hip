@@ -25,22 +25,13 @@
 #include <thread>
 #include <vector>
 
+#include "device_guard.h"
 #include "agile_guard.h"
 #include "ring.h"
 
 namespace {
 
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = false;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) return;
-        ok = prev == dev || hipSetDevice(dev) == hipSuccess;
-    }
-    ~DeviceGuard() {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
+using agile::DeviceGuard;
 
 struct Slot {
     hipStream_t stream = nullptr;

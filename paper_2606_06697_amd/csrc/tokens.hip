@@ -20,6 +20,7 @@
 #include <set>
 #include <vector>
 
+#include "device_guard.h"
 #include "agile_guard.h"
 
 namespace agile {
@@ -92,17 +93,7 @@ __global__ __launch_bounds__(TBLOCK) void k_tokens_check(
 }  // namespace agile
 
 namespace {
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = false;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) return;
-        ok = prev == dev || hipSetDevice(dev) == hipSuccess;
-    }
-    ~DeviceGuard() {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
+using agile::DeviceGuard;
 }  // namespace
 
 using agile::GEN_MASK;
