@@ -4,10 +4,11 @@
  * Implements the data-parallel part of the protected GPU memory model of AgileOS
  * (arXiv 2606.06697): an allocation table that separates user allocations from protected
  * module and MMIO ranges (Section IV-E, Table I; Section V-A records each allocation's base
- * and live size), batched API-time pointer validation (Section IV-E, V-C), and guarded
- * kernels whose every global access is checked before it happens, with the paper's
- * "poison" (record, fail later) and "sink" (redirect to a quarantine page) policies
- * (Section V-E).
+ * and live size), batched API-time pointer validation and the DMA registration check
+ * (Section IV-E, V-C), and guarded kernels whose every global access is checked before it
+ * happens, with the paper's poison (record, fail later), sink (to a zero page) and trap
+ * (retire) policies (Section V-E). Around them: client handle tokens (Section IV-C), a batched
+ * multi-client launch and a native serving loop with revocation (Sections IV-B, IV-D).
  *
  * Conventions for every entry point
  *  - Return value: AGILE_OK (0) or a negative AGILE_E* code; nothing is thrown across the
