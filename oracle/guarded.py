@@ -23,7 +23,14 @@ redirects the access to quarantine memory. This module restates that guard per a
   ``[0, 2**64)``.
 
 Policies: ``SUPPRESS_LOG`` (the ``sink`` to a zero page plus the ``poison`` record),
-``SUPPRESS_ONLY`` (the sink alone) and ``TRAP``. The paper's ``trap`` stops at a violation and
+``SUPPRESS_ONLY`` (the sink alone), ``TRAP``, ``SINK`` and ``REPORT``. Under ``SINK`` a denied
+access is redirected to a caller-provided quarantine of ``qsize`` bytes (a power of two) at
+``qbase``: the access of width ``w`` at ``A`` goes to ``qbase + ((A mod 2**64) mod qsize)``
+rounded down to a multiple of ``w`` (loads read it, stores write it, scatter-add adds into
+it). Under ``REPORT`` a denied access is performed at ``A`` itself when ``[A, A+w)`` lies inside
+one registered range of any kind (memory the table vouches for), and suppressed otherwise
+(memory outside every range may not be mapped). Both log every denial like ``SUPPRESS_LOG``.
+Only the per-access loops define them. The paper's ``trap`` stops at a violation and
 may leave the worker's context unusable, so the worker is retired (Section V-E; Section IV-D,
 lifetime and revocation). Restated per call (``guarded_call``): a call of a retired handle does
 nothing and reports ``ETRAPPED``; a ``TRAP`` call runs as under ``SUPPRESS_LOG`` (the denied
@@ -47,7 +54,7 @@ import numpy as np
 from .table import ALLOW, V_CROSS_ALLOC, V_UNMAPPED, U64_MAX
 
 OP_COPY, OP_TRIAD, OP_GATHER, OP_SCATTER, OP_SCATTER_ADD = 1, 2, 3, 4, 5
-SUPPRESS_LOG, SUPPRESS_ONLY, TRAP = 0, 1, 2
+SUPPRESS_LOG, SUPPRESS_ONLY, TRAP, SINK, REPORT = 0, 1, 2, 3, 4
 OK, ETRAPPED = 0, -8
 _DT = {4: np.float32, 8: np.float64}
 
@@ -93,15 +100,51 @@ def _allowed(bind, A, w):
 
 
 class _Denier:
-    def __init__(self, table, log, seq, op, policy):
-        if policy not in (SUPPRESS_LOG, SUPPRESS_ONLY, TRAP):
+    def __init__(self, table, log, seq, op, policy, quarantine=None, loops=True):
+        if policy not in (SUPPRESS_LOG, SUPPRESS_ONLY, TRAP, SINK, REPORT):
             raise ValueError("unknown policy")
+        if policy in (SINK, REPORT) and not loops:
+            raise NotImplementedError("the redirecting policies are defined by the loop forms")
+        if policy == SINK:
+            qb, qs = quarantine
+            if qs < 256 or qs & (qs - 1):
+                raise ValueError("quarantine size must be a power of two >= 256")
         self.t, self.log, self.seq, self.op = table, log, seq, op
+        self.policy, self.q = policy, quarantine
         self.on = policy != SUPPRESS_ONLY
 
     def __call__(self, elem, operand, A, w):
         if self.on:
             self.log.offer(self.t, self.seq, elem, operand, A, w, self.op)
+
+    def target(self, A, w):
+        """Where a denied access of width w at exact address A goes (None: suppressed)."""
+        if self.policy == SINK:
+            qb, qs = self.q
+            return qb + ((A % (1 << 64)) % qs) // w * w
+        if self.policy == REPORT:
+            if A < 0 or A + w > (1 << 64):
+                return None
+            ent = self.t.owner_entry(A)
+            if ent is not None and A + w <= ent[1]:
+                return A
+        return None
+
+    def load(self, mem, A, w):
+        """The bytes a denied load reads."""
+        t = self.target(A, w)
+        return bytes(w) if t is None else mem.read(t, w)
+
+    def store(self, mem, A, data):
+        t = self.target(A, len(data))
+        if t is not None:
+            mem.write(t, data)
+
+    def add(self, mem, A, val, dt):
+        t = self.target(A, dt().itemsize)
+        if t is not None:
+            old = np.frombuffer(mem.read(t, dt().itemsize), dtype=dt)[0]
+            mem.write(t, dt(old + val).tobytes())
 
 
 def guarded_call(kernel, table, mem, log, seq, *args, policy=SUPPRESS_LOG, **kw):
@@ -121,20 +164,21 @@ def guarded_call(kernel, table, mem, log, seq, *args, policy=SUPPRESS_LOG, **kw)
 
 
 # ------------------------------------------------------------------ per-access loops
-def copy_loop(table, mem, log, seq, dst, src, n, policy=SUPPRESS_LOG):
-    deny = _Denier(table, log, seq, OP_COPY, policy)
+def copy_loop(table, mem, log, seq, dst, src, n, policy=SUPPRESS_LOG, quarantine=None):
+    deny = _Denier(table, log, seq, OP_COPY, policy, quarantine)
     bs, bd = table.binding(src), table.binding(dst)
     for k in range(n):
         A = src + k
         if _allowed(bs, A, 1):
             byte = mem.read(A, 1)
         else:
-            byte = b"\0"
+            byte = deny.load(mem, A, 1)
             deny(k, 0, A, 1)
         A = dst + k
         if _allowed(bd, A, 1):
             mem.write(A, byte)
         else:
+            deny.store(mem, A, byte)
             deny(k, 1, A, 1)
 
 
@@ -142,8 +186,8 @@ def _f32(b: bytes):
     return np.frombuffer(b, dtype=np.float32)[0]
 
 
-def triad_loop(table, mem, log, seq, a, b, c, s, n, policy=SUPPRESS_LOG):
-    deny = _Denier(table, log, seq, OP_TRIAD, policy)
+def triad_loop(table, mem, log, seq, a, b, c, s, n, policy=SUPPRESS_LOG, quarantine=None):
+    deny = _Denier(table, log, seq, OP_TRIAD, policy, quarantine)
     ba, bb, bc = table.binding(a), table.binding(b), table.binding(c)
     s32 = np.float32(s)
     for i in range(n):
@@ -153,7 +197,7 @@ def triad_loop(table, mem, log, seq, a, b, c, s, n, policy=SUPPRESS_LOG):
             if _allowed(bind, A, 4):
                 vals.append(_f32(mem.read(A, 4)))
             else:
-                vals.append(np.float32(0.0))
+                vals.append(_f32(deny.load(mem, A, 4)))
                 deny(i, op_i, A, 4)
         prod = np.float32(s32 * vals[1])          # first rounding
         r = np.float32(vals[0] + prod)            # second rounding
@@ -161,6 +205,7 @@ def triad_loop(table, mem, log, seq, a, b, c, s, n, policy=SUPPRESS_LOG):
         if _allowed(ba, A, 4):
             mem.write(A, np.float32(r).tobytes())
         else:
+            deny.store(mem, A, np.float32(r).tobytes())
             deny(i, 2, A, 4)
 
 
@@ -169,12 +214,12 @@ def _idx_load(mem, bind, idx_ptr, i, deny, elem):
     if _allowed(bind, A, 8):
         return int(np.frombuffer(mem.read(A, 8), dtype=np.int64)[0])
     deny(elem, 0, A, 8)
-    return 0
+    return int(np.frombuffer(deny.load(mem, A, 8), dtype=np.int64)[0])
 
 
 def gather_loop(table, mem, log, seq, out, T, row_bytes, idx_ptr, n, w=4,
-                policy=SUPPRESS_LOG):
-    deny = _Denier(table, log, seq, OP_GATHER, policy)
+                policy=SUPPRESS_LOG, quarantine=None):
+    deny = _Denier(table, log, seq, OP_GATHER, policy, quarantine)
     D = row_bytes // w
     bi, bt, bo = table.binding(idx_ptr), table.binding(T), table.binding(out)
     for i in range(n):
@@ -185,18 +230,20 @@ def gather_loop(table, mem, log, seq, out, T, row_bytes, idx_ptr, n, w=4,
             if _allowed(bt, A, w):
                 val = mem.read(A, w)
             else:
-                val = bytes(w)
+                val = deny.load(mem, A, w)
                 deny(e, 1, A, w)
             A = out + i * row_bytes + col * w
             if _allowed(bo, A, w):
                 mem.write(A, val)
             else:
+                deny.store(mem, A, val)
                 deny(e, 2, A, w)
 
 
 def scatter_loop(table, mem, log, seq, dst, row_bytes, idx_ptr, src, n, w=4, accumulate=False,
-                 policy=SUPPRESS_LOG):
-    deny = _Denier(table, log, seq, OP_SCATTER_ADD if accumulate else OP_SCATTER, policy)
+                 policy=SUPPRESS_LOG, quarantine=None):
+    deny = _Denier(table, log, seq, OP_SCATTER_ADD if accumulate else OP_SCATTER, policy,
+                   quarantine)
     D = row_bytes // w
     dt = _DT[w]
     bi, bs, bd = table.binding(idx_ptr), table.binding(src), table.binding(dst)
@@ -208,7 +255,7 @@ def scatter_loop(table, mem, log, seq, dst, row_bytes, idx_ptr, src, n, w=4, acc
             if _allowed(bs, A, w):
                 val = mem.read(A, w)
             else:
-                val = bytes(w)
+                val = deny.load(mem, A, w)
                 deny(e, 1, A, w)
             A = dst + iv * row_bytes + col * w
             if _allowed(bd, A, w):
@@ -219,6 +266,10 @@ def scatter_loop(table, mem, log, seq, dst, row_bytes, idx_ptr, src, n, w=4, acc
                 else:
                     mem.write(A, val)
             else:
+                if accumulate:
+                    deny.add(mem, A, np.frombuffer(val, dtype=dt)[0], dt)
+                else:
+                    deny.store(mem, A, val)
                 deny(e, 2, A, w)
 
 
@@ -247,7 +298,7 @@ def _first_denied_col(c0, c1, D):
 
 
 def copy_vec(table, mem, log, seq, dst, src, n, policy=SUPPRESS_LOG):
-    deny = _Denier(table, log, seq, OP_COPY, policy)
+    deny = _Denier(table, log, seq, OP_COPY, policy, loops=False)
     bs, bd = table.binding(src), table.binding(dst)
     ks = max(0, min(n, bs[1] - src)) if bs[0] <= src else 0
     kd = max(0, min(n, bd[1] - dst)) if bd[0] <= dst else 0
@@ -267,7 +318,7 @@ def copy_vec(table, mem, log, seq, dst, src, n, policy=SUPPRESS_LOG):
 
 
 def triad_vec(table, mem, log, seq, a, b, c, s, n, policy=SUPPRESS_LOG):
-    deny = _Denier(table, log, seq, OP_TRIAD, policy)
+    deny = _Denier(table, log, seq, OP_TRIAD, policy, loops=False)
     i = np.arange(n, dtype=np.int64) * 4
     vals = []
     cands = []
@@ -406,7 +457,7 @@ def _count_and_first(D, n, idx_bad, groups):
 
 
 def gather_vec(table, mem, log, seq, out, T, row_bytes, idx_ptr, n, w=4, policy=SUPPRESS_LOG):
-    deny = _Denier(table, log, seq, OP_GATHER, policy)
+    deny = _Denier(table, log, seq, OP_GATHER, policy, loops=False)
     D = row_bytes // w
     iv, idx_bad = _read_idx_vec(table, mem, idx_ptr, n)
     roff_t = iv.astype(object) * row_bytes
@@ -428,7 +479,7 @@ def gather_vec(table, mem, log, seq, out, T, row_bytes, idx_ptr, n, w=4, policy=
 def scatter_vec(table, mem, log, seq, dst, row_bytes, idx_ptr, src, n, w=4, accumulate=False,
                 policy=SUPPRESS_LOG):
     op = OP_SCATTER_ADD if accumulate else OP_SCATTER
-    deny = _Denier(table, log, seq, op, policy)
+    deny = _Denier(table, log, seq, op, policy, loops=False)
     D = row_bytes // w
     iv, idx_bad = _read_idx_vec(table, mem, idx_ptr, n)
     roff_s = np.arange(n, dtype=np.int64).astype(object) * row_bytes

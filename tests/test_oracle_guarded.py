@@ -56,6 +56,7 @@ def scenario(seed):
     addr["P"] = (BASE + 896, BASE + 1024)
     user("C", BASE + 2048, 1000)                   # hole [1024, 2048) before it
     t.insert(BASE + 4096, 64, MMIO)
+    mem.add(BASE + 4096, np.full(64, 0x3C, np.uint8))    # backed (REPORT may touch it)
     addr["M"] = (BASE + 4096, BASE + 4160)
     user("I", BASE + 8192, 8 * 64)                 # index buffer
     return t, mem, addr
@@ -463,3 +464,150 @@ def test_trap_policy_retires_on_a_violation_only():
         assert G.guarded_call(G.gather_vec, t, mem, log2, 5, C[0] + 200, A[0], 4, idx_ptr, 3,
                               policy=pol) == G.OK
     assert not log2.retired and log2.count == 1
+
+
+# --- redirecting policies: sink to a quarantine, report ---------------------------------
+Q_BASE, Q_SIZE = 0x5000_0000, 256
+
+
+def _with_quarantine(mem, fill=0):
+    mem.add(Q_BASE, np.full(Q_SIZE, fill, np.uint8) if np.isscalar(fill)
+            else np.asarray(fill, np.uint8))
+    return (Q_BASE, Q_SIZE)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_redirecting_policies_log_like_suppress_for_copy_and_triad(seed):
+    """Copy and triad deny by position only, so their logs under SINK and REPORT equal the
+    SUPPRESS_LOG log exactly."""
+    t, mem, addr = scenario(seed)
+    rng = random.Random(seed)
+    ptrs = pointer_choices(addr)
+    for trial in range(25):
+        dst, src, c = rng.choice(ptrs), rng.choice(ptrs), rng.choice(ptrs)
+        n = rng.choice([1, 7, 64, 300])
+        if _overlap(dst, n, src, n) or dst == src:
+            continue
+        ref = RecordingLog()
+        G.copy_loop(t, copy.deepcopy(mem), ref, trial, dst, src, n)
+        for pol in (G.SINK, G.REPORT):
+            m = copy.deepcopy(mem)
+            q = _with_quarantine(m, 7)
+            log = G.FaultLog()
+            G.copy_loop(t, m, log, trial, dst, src, n, pol, quarantine=q)
+            _logs_equal(log, ref)
+        if _overlap(dst, 4 * n, src, 4 * n) or _overlap(dst, 4 * n, c, 4 * n) or dst % 4:
+            continue
+        ref = RecordingLog()
+        G.triad_loop(t, copy.deepcopy(mem), ref, trial, dst, src, c, 2.0, n)
+        for pol in (G.SINK, G.REPORT):
+            m = copy.deepcopy(mem)
+            log = G.FaultLog()
+            G.triad_loop(t, m, log, trial, dst, src, c, 2.0, n, pol,
+                         quarantine=_with_quarantine(m))
+            _logs_equal(log, ref)
+
+
+def test_sink_by_hand():
+    """A 16-byte copy whose source runs 6 bytes past its allocation into a hole and whose
+    destination runs 4 bytes past its own: the denied source bytes read the quarantine at
+    (address mod 256), the denied destination bytes land there. Values derived by hand."""
+    t, mem = RangeTable(), Memory()
+    src, dst = BASE + 0x100 - 10, BASE + 0x400 - 12        # 10 readable, 12 writable bytes
+    t.insert(BASE, 0x100, USER)
+    mem.add(BASE, np.arange(0x100, dtype=np.uint8))
+    t.insert(BASE + 0x300, 0x100, USER)
+    mem.add(BASE + 0x300, np.zeros(0x100, np.uint8))
+    mem.add(BASE + 0x100, np.zeros(0x40, np.uint8))         # backed but unregistered
+    mem.add(BASE + 0x400, np.full(0x40, 0xEE, np.uint8))
+    q = _with_quarantine(mem, np.arange(Q_SIZE, dtype=np.uint8) ^ 0x5A)
+    log = G.FaultLog()
+    G.copy_loop(t, mem, log, 0, dst, src, 16, G.SINK, quarantine=q)
+    got = mem.read(dst, 12)
+    # bytes 0..9 from the source (0xF6..0xFF), bytes 10, 11 from the quarantine slots of
+    # src + 10 = BASE + 0x100 and src + 11 (offsets 0x00, 0x01 mod 256)
+    assert got == bytes(range(0xF6, 0x100)) + bytes([0x00 ^ 0x5A, 0x01 ^ 0x5A])
+    # destination bytes 12..15 (addresses BASE + 0x400 .. 0x403) go to quarantine 0x00..0x03,
+    # carrying source bytes 12..15, which themselves came from quarantine 0x02..0x05
+    assert mem.read(Q_BASE, 4) == bytes([0x02 ^ 0x5A, 0x03 ^ 0x5A, 0x04 ^ 0x5A, 0x05 ^ 0x5A])
+    assert mem.read(BASE + 0x400, 4) == bytes([0xEE] * 4)   # never written
+    assert log.count == 6 + 4
+
+
+def test_sink_aligns_the_slot_to_the_access_width():
+    t, mem = RangeTable(), Memory()
+    t.insert(BASE, 64, USER)
+    mem.add(BASE, np.zeros(64, np.uint8))
+    idx = np.array([0, 16 + 3], np.int64)        # row 19 of 4-byte rows: 12 bytes past the end
+    t.insert(BASE + 0x1000, 16, USER)
+    mem.add(BASE + 0x1000, idx.view(np.uint8))
+    t.insert(BASE + 0x2000, 8, USER)
+    mem.add(BASE + 0x2000, np.zeros(8, np.uint8))
+    q = _with_quarantine(mem, np.arange(Q_SIZE, dtype=np.uint8))
+    # a table pointer 2 bytes into the allocation (the oracle takes any pointer; the library
+    # requires element alignment, where the rounding changes nothing)
+    G.gather_loop(t, mem, G.FaultLog(), 0, BASE + 0x2000, BASE + 2, 4, BASE + 0x1000, 2, 4,
+                  G.SINK, quarantine=q)
+    # row 19 is at BASE + 78: (BASE + 78) mod 256 = 78, rounded down to the width: slot 76
+    assert mem.read(BASE + 0x2004, 4) == bytes([76, 77, 78, 79])
+
+
+def test_report_performs_only_inside_registered_ranges():
+    """Under REPORT a denied access into another registered range (any kind) happens, exactly
+    as an unguarded read or write of that address would; one into unregistered memory is
+    suppressed, exactly as under SUPPRESS_LOG; both are logged like SUPPRESS_LOG."""
+    t, mem, addr = scenario(5)
+    A0, P0 = addr["A"][0], addr["P"][0]
+    rows = [3, (addr["B"][0] - A0) // 4 + 2, (P0 - A0) // 4 + 1, (BASE + 1500 - A0) // 4]
+    for pol in (G.REPORT, G.SUPPRESS_LOG):
+        m = copy.deepcopy(mem)
+        idx_ptr = _write_idx(m, addr, rows)
+        log = RecordingLog()
+        G.gather_loop(t, m, log, 0, addr["C"][0], A0, 4, idx_ptr, len(rows), 4, pol)
+        got = [m.read(addr["C"][0] + 4 * k, 4) for k in range(len(rows))]
+        plain = [m.read(A0 + 4 * r, 4) for r in rows[:3]]   # an unguarded gather's reads
+        if pol == G.REPORT:
+            assert got[:3] == plain and got[3] == bytes(4)      # row 3: an unbacked hole
+            rep_log = (log.count, log.first)
+        else:
+            assert got == [plain[0], bytes(4), bytes(4), bytes(4)]
+            assert (log.count, log.first) == rep_log
+    # a denied store into the protected canary happens under REPORT
+    m = copy.deepcopy(mem)
+    G.copy_loop(t, m, G.FaultLog(), 0, P0, A0, 8, G.REPORT)
+    assert m.read(P0, 8) == m.read(A0, 8) != bytes([0xA5] * 8)
+
+
+def test_sink_with_a_zero_quarantine_and_no_denied_store_equals_suppress():
+    """Denied loads that read an all-zero quarantine give the suppressed value."""
+    t, mem, addr = scenario(6)
+    rng = random.Random(6)
+    rows = hostile_indices(rng, 128, 40)
+    D = 2
+    m1, m2 = copy.deepcopy(mem), copy.deepcopy(mem)
+    for m in (m1, m2):
+        idx_ptr = _write_idx(m, addr, rows)
+    G.gather_loop(t, m1, G.FaultLog(), 0, addr["C"][0], addr["A"][0], 4 * D, idx_ptr, 40, 4)
+    G.gather_loop(t, m2, G.FaultLog(), 0, addr["C"][0], addr["A"][0], 4 * D, idx_ptr, 40, 4,
+                  G.SINK, quarantine=_with_quarantine(m2))
+    _same(m1, m2, addr)
+
+
+def test_sink_scatter_add_accumulates_in_the_quarantine():
+    t, mem = RangeTable(), Memory()
+    t.insert(BASE, 16, USER)                                  # dst: 4 fp32 rows of 1
+    mem.add(BASE, np.zeros(4, np.float32).view(np.uint8))
+    idx = np.array([1, 4, 4, 9], np.int64)                    # rows 4 and 9 are past the end
+    t.insert(BASE + 0x1000, 32, USER)
+    mem.add(BASE + 0x1000, idx.view(np.uint8))
+    src = np.array([1.0, 2.0, 3.0, 4.0], np.float32)
+    t.insert(BASE + 0x2000, 16, USER)
+    mem.add(BASE + 0x2000, src.view(np.uint8))
+    q = _with_quarantine(mem)
+    G.scatter_loop(t, mem, G.FaultLog(), 0, BASE, 4, BASE + 0x1000, BASE + 0x2000, 4, 4, True,
+                   G.SINK, quarantine=q)
+    dst = np.frombuffer(mem.read(BASE, 16), np.float32)
+    assert dst.tolist() == [0.0, 1.0, 0.0, 0.0]
+    quar = np.frombuffer(mem.read(Q_BASE, Q_SIZE), np.float32)
+    # row 4 -> BASE + 16 (slot 16 / 4 = 4), row 9 -> BASE + 36 (slot 9)
+    assert quar[4] == 5.0 and quar[9] == 4.0 and quar.sum() == 9.0

@@ -40,7 +40,13 @@ GUARD_CHECKS = ([PG.test_access_straddling_the_allocation_end_is_denied,
                  PG.test_triad_matches_exact_rational_rounding,
                  PG.test_scatter_add_unit_gradient_counts, PG.test_fault_reason_codes,
                  PG.test_gather_no_fault_is_take, PG.test_copy_partial_closed_form_values,
-                 PG.test_trap_policy_retires_on_a_violation_only] +
+                 PG.test_trap_policy_retires_on_a_violation_only, PG.test_sink_by_hand,
+                 PG.test_sink_aligns_the_slot_to_the_access_width,
+                 PG.test_report_performs_only_inside_registered_ranges,
+                 PG.test_sink_with_a_zero_quarantine_and_no_denied_store_equals_suppress,
+                 PG.test_sink_scatter_add_accumulates_in_the_quarantine] +
+                [lambda s=s: PG.test_redirecting_policies_log_like_suppress_for_copy_and_triad(s)
+                 for s in range(4)] +
                 [lambda s=s: PG.test_copy_vec_matches_loop(s) for s in range(6)] +
                 [lambda s=s: PG.test_triad_vec_matches_loop(s) for s in range(4)] +
                 [lambda s=s, w=w, D=D: PG.test_gather_vec_matches_loop(s, w, D)
@@ -194,6 +200,46 @@ def _trapping_call_rolled_back(orig):
             mem.__dict__.update(snap.__dict__)
         return rc
     return guarded_call
+
+
+def _target_unaligned(self, A, w):
+    if self.policy == G.SINK:
+        qb, qs = self.q
+        return qb + (A % (1 << 64)) % qs
+    return _ORIG_TARGET(self, A, w)
+
+
+def _target_report_everywhere(self, A, w):
+    if self.policy == G.REPORT:
+        return A
+    return _ORIG_TARGET(self, A, w)
+
+
+def _store_dropped(self, mem, A, data):
+    return None
+
+
+def _add_overwrites(self, mem, A, val, dt):
+    t = self.target(A, dt().itemsize)
+    if t is not None:
+        mem.write(t, dt(val).tobytes())
+
+
+_ORIG_TARGET = G._Denier.target
+
+DENIER_MUTANTS = {
+    "sink slot not aligned to the access width": ("target", _target_unaligned),
+    "report performs outside registered ranges": ("target", _target_report_everywhere),
+    "redirected stores dropped": ("store", _store_dropped),
+    "redirected scatter-add overwrites": ("add", _add_overwrites),
+}
+
+
+@pytest.mark.parametrize("name", sorted(DENIER_MUTANTS))
+def test_redirect_mistake_is_caught(name, monkeypatch):
+    attr, fn = DENIER_MUTANTS[name]
+    monkeypatch.setattr(G._Denier, attr, fn)
+    assert _fails(GUARD_CHECKS), name
 
 
 GUARD_MUTANTS = {
