@@ -85,7 +85,24 @@ enum {
  * naming it return AGILE_ETRAPPED before queuing anything; agile_rt_remove (revocation),
  * agile_rt_count, agile_fault_log_read (which then returns AGILE_ETRAPPED) and
  * agile_rt_destroy still work. Retirement lasts until the handle is destroyed. */
-enum { AGILE_POLICY_SUPPRESS_LOG = 0, AGILE_POLICY_SUPPRESS_ONLY = 1, AGILE_POLICY_TRAP = 2 };
+enum {
+    AGILE_POLICY_SUPPRESS_LOG = 0,
+    AGILE_POLICY_SUPPRESS_ONLY = 1,
+    AGILE_POLICY_TRAP = 2,
+    AGILE_POLICY_SINK = 3,
+    AGILE_POLICY_REPORT = 4
+};
+/* SINK (Section V-E "sink": redirect to quarantine memory, for debugging, without isolation
+ * between violations): a denied access of width w at exact address A goes to the handle's
+ * quarantine (agile_rt_set_quarantine) at offset (A mod 2^64) mod qsize, rounded down to a
+ * multiple of w: denied loads read it, denied stores write it, denied scatter-adds add into it
+ * (atomically). REPORT (Section V-E "report": log would-be violations without enforcing): a
+ * denied access is performed at A when [A, A+w) lies inside one registered range of the table
+ * (any kind); outside every range it stays suppressed, since such memory may not be mapped.
+ * Both log every denial as SUPPRESS_LOG does, and both run a second pass after the guarded
+ * kernel on the same stream. Denied accesses of one call that reach the same quarantine slot
+ * or address are unordered (like duplicate indices of a plain scatter). SINK without a
+ * quarantine is EINVAL. */
 
 /* Guarded operations, as recorded in a fault record. */
 enum {
@@ -157,6 +174,11 @@ int agile_rt_insert_many(agile_rt* rt, const uint64_t* base, const uint64_t* siz
  * reports UNMAPPED there (freed allocations are rejected, Section IV-E, V-C).
  * Errors: EINVAL, ENOENT. */
 int agile_rt_remove(agile_rt* rt, int32_t id);
+
+/* Set the quarantine of the SINK policy: caller-owned device memory of `bytes` bytes (a power
+ * of two, 256 .. 2^40, 256-byte aligned), used by later SINK calls until replaced; NULL and 0
+ * remove it. The library never frees it. Errors: EINVAL. */
+int agile_rt_set_quarantine(agile_rt* rt, void* d_quarantine, uint64_t bytes);
 
 /* Remove every range: the end of a client's assignment revokes all of its allocations
  * (Section IV-D, lifetime and revocation). Ids are not reused afterwards. Launches queued

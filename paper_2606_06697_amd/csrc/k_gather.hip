@@ -322,14 +322,15 @@ static void gather_w(const DevTable& t, DevLog* log, void* out, const void* tab,
 
 hipError_t launch_gather(bool guard, const DevTable& t, DevLog* log, const Bind* binds, void* out,
                          const void* tab, uint64_t rb, const int64_t* idx, uint64_t n, uint32_t w,
-                         unsigned long long seq, int logon, const DevInfo& d, hipStream_t s) {
+                         unsigned long long seq, int logon, const DevInfo& d, hipStream_t s,
+                         bool finish) {
     if (n == 0) return hipSuccess;
     if (guard) {
         const RowsGuard rg = rows_guard(binds[0], binds[2], binds[1], (uint64_t)idx, (uint64_t)out,
                                         (uint64_t)tab, n, rb, w);
         if (w == 4) gather_w<true, 4>(t, log, out, tab, rb, idx, n, rg, seq, logon, d, s);
         else gather_w<true, 8>(t, log, out, tab, rb, idx, n, rg, seq, logon, d, s);
-        if (logon)
+        if (logon && finish)
             return launch_fault_finish(t, log, rows_fault_site(3 /*OP_GATHER*/, w, 1, rb, rg.ki, idx,
                                                                  out, tab), seq, s);
     } else {
@@ -373,17 +374,17 @@ static void scatter_w(const DevTable& t, DevLog* log, void* dst, uint64_t rb, co
 hipError_t launch_scatter(bool guard, const DevTable& t, DevLog* log, const Bind* binds, void* dst,
                           uint64_t rb, const int64_t* idx, const void* src, uint64_t n, uint32_t w,
                           int accumulate, unsigned long long seq, int logon, void* scratch,
-                          const DevInfo& d, hipStream_t s) {
+                          const DevInfo& d, hipStream_t s, bool finish) {
     if (n == 0) return hipSuccess;
     if (accumulate)
         return launch_scatter_add(guard, t, log, binds, dst, rb, idx, src, n, w, seq, logon,
-                                  scratch, d, s);
+                                  scratch, d, s, finish);
     if (guard) {
         const RowsGuard rg = rows_guard(binds[0], binds[1], binds[2], (uint64_t)idx, (uint64_t)src,
                                         (uint64_t)dst, n, rb, w);
         if (w == 4) scatter_w<true, 4>(t, log, dst, rb, idx, src, n, rg, seq, logon, d, s);
         else scatter_w<true, 8>(t, log, dst, rb, idx, src, n, rg, seq, logon, d, s);
-        if (logon)
+        if (logon && finish)
             return launch_fault_finish(t, log, rows_fault_site(4 /*OP_SCATTER*/, w, 2, rb, rg.ki, idx,
                                                                  src, dst), seq, s);
     } else {

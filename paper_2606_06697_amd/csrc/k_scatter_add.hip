@@ -642,7 +642,7 @@ static void scatter_add_w(const DevTable& t, DevLog* log, void* dst, uint64_t rb
 hipError_t launch_scatter_add(bool guard, const DevTable& t, DevLog* log, const Bind* binds,
                               void* dst, uint64_t rb, const int64_t* idx, const void* src,
                               uint64_t n, uint32_t w, unsigned long long seq, int logon,
-                              void* scratch, const DevInfo& d, hipStream_t s) {
+                              void* scratch, const DevInfo& d, hipStream_t s, bool finish) {
     if (n == 0) return hipSuccess;
     const RowsGuard rg = guard ? rows_guard(binds[0], binds[1], binds[2], (uint64_t)idx,
                                             (uint64_t)src, (uint64_t)dst, n, rb, w)
@@ -680,7 +680,7 @@ hipError_t launch_scatter_add(bool guard, const DevTable& t, DevLog* log, const 
         if (w == 4) scatter_add_w<false, 4>(t, log, dst, rb, idx, src, n, rg, seq, logon, d, s);
         else scatter_add_w<false, 8>(t, log, dst, rb, idx, src, n, rg, seq, logon, d, s);
     }
-    if (guard && logon)
+    if (guard && logon && finish)
         return launch_fault_finish(t, log, rows_fault_site(5 /*OP_SCATTER_ADD*/, w, 2, rb, rg.ki, idx,
                                                              src, dst), seq, s);
     return hipGetLastError();

@@ -32,10 +32,12 @@ hipError_t launch_triad(bool guard, const DevTable& t, DevLog* log, const Bind* 
                         const float* b, const float* c, float sc, uint64_t n,
                         unsigned long long seq, int logon, const DevInfo& d, hipStream_t s);
 
+// finish == false leaves the launch's denials in the log scratch for a later kernel (the
+// redirecting policies' pass) and the finishing kernel.
 hipError_t launch_gather(bool guard, const DevTable& t, DevLog* log, const Bind* binds, void* out,
                          const void* tab, uint64_t row_bytes, const int64_t* idx, uint64_t n,
                          uint32_t w, unsigned long long seq, int logon, const DevInfo& d,
-                         hipStream_t s);
+                         hipStream_t s, bool finish = true);
 
 // Scatter with accumulate = 1 uses `scratch` (device memory of at least
 // scatter_add_scratch_bytes(n) bytes, or null for the chunk path) for its sort; calls that share
@@ -43,12 +45,12 @@ hipError_t launch_gather(bool guard, const DevTable& t, DevLog* log, const Bind*
 hipError_t launch_scatter(bool guard, const DevTable& t, DevLog* log, const Bind* binds, void* dst,
                           uint64_t row_bytes, const int64_t* idx, const void* src, uint64_t n,
                           uint32_t w, int accumulate, unsigned long long seq, int logon,
-                          void* scratch, const DevInfo& d, hipStream_t s);
+                          void* scratch, const DevInfo& d, hipStream_t s, bool finish = true);
 
 hipError_t launch_scatter_add(bool guard, const DevTable& t, DevLog* log, const Bind* binds,
                               void* dst, uint64_t rb, const int64_t* idx, const void* src,
                               uint64_t n, uint32_t w, unsigned long long seq, int logon,
-                              void* scratch, const DevInfo& d, hipStream_t s);
+                              void* scratch, const DevInfo& d, hipStream_t s, bool finish = true);
 
 size_t scatter_add_scratch_bytes(uint64_t n);
 
@@ -56,6 +58,25 @@ size_t scatter_add_scratch_bytes(uint64_t n);
 constexpr uint64_t SORT_MIN_N = 1u << 15;
 
 hipError_t launch_log_reset(DevLog* log, hipStream_t s);
+
+// Redirecting policies (sink to a quarantine, report): the pass after a guarded kernel.
+constexpr uint32_t REDIRECT_SINK = 1, REDIRECT_REPORT = 2;
+struct Redirect {
+    uint32_t mode;
+    uint32_t pad;
+    uint8_t* q;      // quarantine (SINK)
+    uint64_t qmask;  // its size - 1 (a power of two)
+};
+hipError_t launch_copy_fix(const DevTable& t, const Redirect& r, void* dst, const void* src,
+                           uint64_t n, uint64_t Ks, uint64_t Kd, const DevInfo& d, hipStream_t s);
+hipError_t launch_triad_fix(const DevTable& t, const Redirect& r, float* a, const float* b,
+                            const float* c, float sc, uint64_t n, uint64_t Ka, uint64_t Kb,
+                            uint64_t Kc, const DevInfo& d, hipStream_t s);
+// op 0 gather (cont = out, rowp = table), 1 scatter, 2 scatter-add (cont = src, rowp = dst);
+// rg: the guard over all n rows; the guarded kernel ran rows below rg.ki.
+hipError_t launch_rows_fix(int op, const DevTable& t, DevLog* log, const Redirect& r, void* cont,
+                           void* rowp, uint64_t rb, const int64_t* idx, uint64_t n,
+                           const RowsGuard& rg, uint32_t w, const DevInfo& d, hipStream_t s);
 
 // After a guarded row kernel: folds the launch's denial count into the log and records the
 // smallest key if the log is empty.

@@ -79,6 +79,8 @@ struct agile_rt {
     size_t stage_bytes = 0;
     agile_fault* hlog = nullptr;
     unsigned long long* htrap = nullptr;  // log count before / after a TRAP-policy call
+    uint8_t* q_ptr = nullptr;             // quarantine of the SINK policy (caller-owned)
+    uint64_t q_bytes = 0;
     bool retired = false;                 // retired by a TRAP-policy violation
     std::vector<hipStream_t> streams_used;  // streams that launched with the current image
     // sort scratch of the scatter-add (grown on demand)
@@ -520,6 +522,21 @@ int agile_rt_remove(agile_rt* rt, int32_t id) {
     return AGILE_OK;
 }
 
+int agile_rt_set_quarantine(agile_rt* rt, void* d_quarantine, uint64_t bytes) {
+    if (!rt) return AGILE_EINVAL;
+    if (!d_quarantine && bytes == 0) {
+        rt->q_ptr = nullptr;
+        rt->q_bytes = 0;
+        return AGILE_OK;
+    }
+    if (!d_quarantine || bytes < 256 || bytes > (1ull << 40) || (bytes & (bytes - 1)) ||
+        ((uint64_t)d_quarantine & 255))
+        return AGILE_EINVAL;
+    rt->q_ptr = static_cast<uint8_t*>(d_quarantine);
+    rt->q_bytes = bytes;
+    return AGILE_OK;
+}
+
 int agile_rt_clear(agile_rt* rt) {
     if (!rt) return AGILE_EINVAL;
     rt->entries.clear();
@@ -570,7 +587,26 @@ int agile_validate_dma(agile_rt* rt, const agile_ptr* d_q, uint64_t n, uint8_t* 
 
 static bool policy_ok(int policy) {
     return policy == AGILE_POLICY_SUPPRESS_LOG || policy == AGILE_POLICY_SUPPRESS_ONLY ||
-           policy == AGILE_POLICY_TRAP;
+           policy == AGILE_POLICY_TRAP || policy == AGILE_POLICY_SINK ||
+           policy == AGILE_POLICY_REPORT;
+}
+
+static bool redirecting(int policy) {
+    return policy == AGILE_POLICY_SINK || policy == AGILE_POLICY_REPORT;
+}
+
+// The redirect of a SINK or REPORT call (EINVAL: SINK without a quarantine).
+static int redirect_of(const agile_rt* rt, int policy, Redirect* r) {
+    *r = Redirect{};
+    if (policy == AGILE_POLICY_SINK) {
+        if (!rt->q_ptr) return AGILE_EINVAL;
+        r->mode = REDIRECT_SINK;
+        r->q = rt->q_ptr;
+        r->qmask = rt->q_bytes - 1;
+    } else {
+        r->mode = REDIRECT_REPORT;
+    }
+    return AGILE_OK;
 }
 
 // Whether a call's denials go to the log (every policy but SUPPRESS_ONLY).
@@ -634,6 +670,8 @@ int agile_guarded_copy(agile_rt* rt, void* d_dst, const void* d_src, uint64_t nb
                        void* stream) {
     if (!rt || !policy_ok(policy)) return AGILE_EINVAL;
     if (rt->retired) return AGILE_ETRAPPED;
+    Redirect rd;
+    if (redirecting(policy) && redirect_of(rt, policy, &rd) != AGILE_OK) return AGILE_EINVAL;
     DeviceGuard dg(rt->device);
     if (!dg.ok) return AGILE_EDEVICE;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -646,6 +684,11 @@ int agile_guarded_copy(agile_rt* rt, void* d_dst, const void* d_src, uint64_t nb
     if (launch_copy(true, rt->tab, rt->d_log, b, d_dst, d_src, nbytes, seq,
                     log_on(policy), rt->info, s) != hipSuccess)
         return AGILE_EDEVICE;
+    if (redirecting(policy) &&
+        launch_copy_fix(rt->tab, rd, d_dst, d_src, nbytes,
+                        clip_prefix(b[0], (uint64_t)d_src, nbytes, 1),
+                        clip_prefix(b[1], (uint64_t)d_dst, nbytes, 1), rt->info, s) != hipSuccess)
+        return AGILE_EDEVICE;
     return trap_end(rt, policy, s);
 }
 
@@ -653,6 +696,8 @@ int agile_guarded_triad(agile_rt* rt, float* d_a, const float* d_b, const float*
                         uint64_t n, int policy, void* stream) {
     if (!rt || !policy_ok(policy)) return AGILE_EINVAL;
     if (rt->retired) return AGILE_ETRAPPED;
+    Redirect rd;
+    if (redirecting(policy) && redirect_of(rt, policy, &rd) != AGILE_OK) return AGILE_EINVAL;
     if ((((uint64_t)d_a | (uint64_t)d_b | (uint64_t)d_c) & 3) || n > (U64MAX >> 3))
         return AGILE_EINVAL;
     DeviceGuard dg(rt->device);
@@ -667,6 +712,11 @@ int agile_guarded_triad(agile_rt* rt, float* d_a, const float* d_b, const float*
                        host_bind(rt, (uint64_t)d_a)};
     if (launch_triad(true, rt->tab, rt->d_log, b, d_a, d_b, d_c, s_, n, seq,
                      log_on(policy), rt->info, s) != hipSuccess)
+        return AGILE_EDEVICE;
+    if (redirecting(policy) &&
+        launch_triad_fix(rt->tab, rd, d_a, d_b, d_c, s_, n, clip_prefix(b[2], (uint64_t)d_a, n, 4),
+                         clip_prefix(b[0], (uint64_t)d_b, n, 4),
+                         clip_prefix(b[1], (uint64_t)d_c, n, 4), rt->info, s) != hipSuccess)
         return AGILE_EDEVICE;
     return trap_end(rt, policy, s);
 }
@@ -686,6 +736,8 @@ int agile_guarded_gather(agile_rt* rt, void* d_out, const void* d_table, uint64_
                          const int64_t* d_idx, uint64_t n, int dtype, int policy, void* stream) {
     if (!rt || !policy_ok(policy)) return AGILE_EINVAL;
     if (rt->retired) return AGILE_ETRAPPED;
+    Redirect rd;
+    if (redirecting(policy) && redirect_of(rt, policy, &rd) != AGILE_OK) return AGILE_EINVAL;
     uint32_t w;
     int rc = rows_args_ok(row_bytes, n, dtype, d_out, d_table, &w);
     if (rc != AGILE_OK) return rc;
@@ -700,9 +752,23 @@ int agile_guarded_gather(agile_rt* rt, void* d_out, const void* d_table, uint64_
     const unsigned long long seq = rt->seq++;
     const Bind b[3] = {host_bind(rt, (uint64_t)d_idx), host_bind(rt, (uint64_t)d_table),
                        host_bind(rt, (uint64_t)d_out)};
-    if (launch_gather(true, rt->tab, rt->d_log, b, d_out, d_table, row_bytes, d_idx, n, w, seq,
-                      log_on(policy), rt->info, s) != hipSuccess)
+    if (redirecting(policy)) {
+        // the guarded kernel runs the rows whose index is readable, the redirect pass the rest
+        const RowsGuard full = rows_guard(b[0], b[2], b[1], (uint64_t)d_idx, (uint64_t)d_out,
+                                          (uint64_t)d_table, n, row_bytes, w);
+        if (launch_gather(true, rt->tab, rt->d_log, b, d_out, d_table, row_bytes, d_idx, full.ki,
+                          w, seq, 1, rt->info, s, false) != hipSuccess ||
+            launch_rows_fix(0, rt->tab, rt->d_log, rd, d_out, const_cast<void*>(d_table),
+                            row_bytes, d_idx, n, full, w, rt->info, s) != hipSuccess ||
+            launch_fault_finish(rt->tab, rt->d_log,
+                                rows_fault_site(AGILE_OP_GATHER, w, 1, row_bytes, full.ki, d_idx,
+                                                d_out, d_table),
+                                seq, s) != hipSuccess)
+            return AGILE_EDEVICE;
+    } else if (launch_gather(true, rt->tab, rt->d_log, b, d_out, d_table, row_bytes, d_idx, n, w,
+                             seq, log_on(policy), rt->info, s) != hipSuccess) {
         return AGILE_EDEVICE;
+    }
     return trap_end(rt, policy, s);
 }
 
@@ -711,6 +777,8 @@ int agile_guarded_scatter(agile_rt* rt, void* d_dst, uint64_t row_bytes, const i
                           void* stream) {
     if (!rt || !policy_ok(policy) || (accumulate != 0 && accumulate != 1)) return AGILE_EINVAL;
     if (rt->retired) return AGILE_ETRAPPED;
+    Redirect rd;
+    if (redirecting(policy) && redirect_of(rt, policy, &rd) != AGILE_OK) return AGILE_EINVAL;
     uint32_t w;
     int rc = rows_args_ok(row_bytes, n, dtype, d_dst, d_src, &w);
     if (rc != AGILE_OK) return rc;
@@ -728,9 +796,22 @@ int agile_guarded_scatter(agile_rt* rt, void* d_dst, uint64_t row_bytes, const i
     void* scr = (accumulate && n >= SORT_MIN_N)
                     ? grow_scratch(rt->sa_scratch, rt->sa_bytes, scatter_add_scratch_bytes(n))
                     : nullptr;
-    if (launch_scatter(true, rt->tab, rt->d_log, b, d_dst, row_bytes, d_idx, d_src, n, w, accumulate,
-                       seq, log_on(policy), scr, rt->info, s) != hipSuccess)
+    if (redirecting(policy)) {
+        const RowsGuard full = rows_guard(b[0], b[1], b[2], (uint64_t)d_idx, (uint64_t)d_src,
+                                          (uint64_t)d_dst, n, row_bytes, w);
+        if (launch_scatter(true, rt->tab, rt->d_log, b, d_dst, row_bytes, d_idx, d_src, full.ki, w,
+                           accumulate, seq, 1, scr, rt->info, s, false) != hipSuccess ||
+            launch_rows_fix(accumulate ? 2 : 1, rt->tab, rt->d_log, rd, const_cast<void*>(d_src),
+                            d_dst, row_bytes, d_idx, n, full, w, rt->info, s) != hipSuccess ||
+            launch_fault_finish(rt->tab, rt->d_log,
+                                rows_fault_site(accumulate ? AGILE_OP_SCATTER_ADD : AGILE_OP_SCATTER,
+                                                w, 2, row_bytes, full.ki, d_idx, d_src, d_dst),
+                                seq, s) != hipSuccess)
+            return AGILE_EDEVICE;
+    } else if (launch_scatter(true, rt->tab, rt->d_log, b, d_dst, row_bytes, d_idx, d_src, n, w,
+                              accumulate, seq, log_on(policy), scr, rt->info, s) != hipSuccess) {
         return AGILE_EDEVICE;
+    }
     return trap_end(rt, policy, s);
 }
 

@@ -22,7 +22,7 @@ AGILE_ENOENT, AGILE_ENOSPC, AGILE_EDEVICE, AGILE_EFAULTED = -4, -5, -6, -7
 AGILE_ETRAPPED = -8
 KIND_USER, KIND_PROTECTED, KIND_MMIO = 0, 1, 2
 ALLOW, V_PROTECTED, V_STRADDLE, V_UNMAPPED, V_CROSS_ALLOC, V_INEXACT = 0, 1, 2, 3, 4, 5
-POLICY_SUPPRESS_LOG, POLICY_SUPPRESS_ONLY, POLICY_TRAP = 0, 1, 2
+POLICY_SUPPRESS_LOG, POLICY_SUPPRESS_ONLY, POLICY_TRAP, POLICY_SINK, POLICY_REPORT = 0, 1, 2, 3, 4
 OP_COPY, OP_TRIAD, OP_GATHER, OP_SCATTER, OP_SCATTER_ADD = 1, 2, 3, 4, 5
 DTYPE_F32, DTYPE_F64 = 0, 1
 TOKEN_VALID, TOKEN_FORGED, TOKEN_STALE, TOKEN_CROSS_CLIENT, TOKEN_WRONG_KIND = 0, 1, 2, 3, 4
@@ -92,6 +92,7 @@ _SIGS = {
     "agile_token_release": (_int, [_vp, _u64, _u32]),
     "agile_tokens_check": (_int, [_vp, _vp, _vp, _vp, _u64, _vp, _vp, _vp]),
     "agile_rt_clear": (_int, [_vp]),
+    "agile_rt_set_quarantine": (_int, [_vp, _vp, _u64]),
     "agile_server_create": (_int, [ctypes.POINTER(_vp), _vp, _vp, _u32, _vp, _vp,
                                    ctypes.POINTER(agile_server_config), _vp, _u64, _vp, _vp,
                                    _int]),
@@ -296,6 +297,10 @@ def agile_batch_run(cs: int, reqs: np.ndarray, ptrs, nptrs: int, ptr_verdict, pt
 def batch_results(result: torch.Tensor, nreq: int) -> np.ndarray:
     """Copy a device result buffer to host as a RESULT_DTYPE array (synchronizes)."""
     return result[:nreq * RESULT_DTYPE.itemsize].cpu().numpy().view(RESULT_DTYPE).copy()
+
+
+def agile_rt_set_quarantine(rt: int, quarantine, nbytes: int) -> None:
+    _check(lib().agile_rt_set_quarantine(rt, _ptr(quarantine), nbytes), "agile_rt_set_quarantine")
 
 
 def agile_rt_clear(rt: int) -> None:

@@ -60,6 +60,7 @@ def test_argument_errors_fail_closed(L):
     assert L.agile_rt_remove(None, 0) == g.AGILE_EINVAL
     assert L.agile_validate_ptrs(None, 0, 1, 0, 0, 0) == g.AGILE_EINVAL
     assert L.agile_validate_dma(None, 0, 1, 0, 0, 0) == g.AGILE_EINVAL
+    assert L.agile_rt_set_quarantine(None, 0, 0) == g.AGILE_EINVAL
     assert L.agile_tokens_create(None, 16, 1, 0) == g.AGILE_EINVAL
     assert L.agile_tokens_create(ctypes.byref(h), 0, 1, 0) == g.AGILE_EINVAL
     assert L.agile_tokens_create(ctypes.byref(h), (1 << 24) + 1, 1, 0) == g.AGILE_EINVAL

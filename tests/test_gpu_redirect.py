@@ -1,0 +1,184 @@
+"""The redirecting guard policies on the device against the oracle's per-access definition.
+
+SINK sends every denied access to a caller-provided quarantine (slot = address mod its size,
+rounded down to the width); REPORT performs a denied access when it lies inside a registered
+range of any kind and suppresses it otherwise (Section V-E, sink and report). One arena holds:
+a USER table/destination A, a protected canary P, an unregistered hole H, another USER
+allocation X, an index buffer I, a source S, an output C and the quarantine Q (not
+registered). Every registered range is backed by the arena, so REPORT only ever touches arena
+bytes. Values are small integers, so sums are exact in any order, and the whole arena,
+quarantine included, must equal the oracle's memory byte for byte. Within one call the denied
+accesses that reach the same quarantine slot or address are either all loads or all adds
+(their order is unspecified, as for duplicate indices of a plain scatter).
+"""
+import numpy as np
+import pytest
+
+from gpu_util import Arena, Twin, log_matches, need_gpu
+from oracle import guarded as G
+
+pytestmark = pytest.mark.gpu
+
+QSIZE = 4096
+ROWS, NMAX = 1024, 40000
+
+
+def layout(rb):
+    off, o = {}, 0
+    for name, size in (("A", ROWS * rb), ("P", 4096), ("H", 4096), ("X", 8192),
+                       ("I", NMAX * 8), ("S", NMAX * rb), ("C", NMAX * rb), ("Q", QSIZE)):
+        o = (o + 4095) // 4096 * 4096
+        off[name] = (o, o + size)
+        o += size
+    return off, (o + 4095) // 4096 * 4096
+
+
+def setup(w, D, seed):
+    need_gpu()
+    rb = w * D
+    off, size = layout(rb)
+    ar = Arena(size, seed)
+    tw = Twin(16)
+    for k, kind in (("A", 0), ("P", 1), ("X", 0), ("I", 0), ("S", 0), ("C", 0)):
+        lo, hi = off[k]
+        tw.insert(ar.addr(lo), hi - lo, kind)
+    dt = np.float32 if w == 4 else np.float64
+    rng = np.random.default_rng(seed)
+    for k in ("A", "P", "H", "X", "S", "C"):
+        lo, hi = off[k]
+        ar.write(lo, rng.integers(-20, 21, (hi - lo) // w).astype(dt))
+    q0 = off["Q"][0]
+    tw.g.agile_rt_set_quarantine(tw.h, ar.addr(q0), QSIZE)
+    return ar, tw, off, dt, rng
+
+
+def run_both(tw, ar, fn_dev, fn_or, ol, what):
+    fn_dev()
+    fn_or()
+    ar.check(what)
+    log_matches(tw, ol, what)
+
+
+@pytest.mark.parametrize("policy", [G.SINK, G.REPORT])
+@pytest.mark.parametrize("w,D", [(4, 1), (4, 4), (8, 2)])
+def test_gather_and_scatter_redirected(policy, w, D):
+    ar, tw, off, dt, rng = setup(w, D, 11 + w + D + policy)
+    g = tw.g
+    rb = w * D
+    A, I, S, C, Q = (ar.addr(off[k][0]) for k in ("A", "I", "S", "C", "Q"))
+    quar = (Q, QSIZE)
+    # quarantine: small valid row numbers as int64 (read by denied index loads) and values
+    qv = np.zeros(QSIZE // 8, np.int64)
+    qv[:] = rng.integers(0, ROWS, qv.size)
+    ar.write(off["Q"][0], qv)
+    ol = G.FaultLog()
+    past = [ROWS + k for k in range(0, (4096 + 4096 + 8192) // rb, 7)]   # into P, H and X
+    before = [-1, -2, -(1 << 40)]
+    n = 600
+    # 1. denied table loads only (rows past the table and before it), all outputs allowed
+    idx = rng.integers(0, ROWS, n).astype(np.int64)
+    pos = rng.choice(n, len(past) + len(before), replace=False)
+    idx[pos] = past + before
+    ar.write(off["I"][0], idx)
+    run_both(tw, ar, lambda: g.agile_guarded_gather(tw.h, C, A, rb, I, n, 0 if w == 4 else 1,
+                                                    policy),
+             lambda: G.gather_loop(tw.ot, ar.mem, ol, tw.next_seq(), C, A, rb, I, n, w, policy,
+                                   quarantine=quar), ol, "gather, denied loads")
+    # 2. denied index loads: the index buffer ends 100 rows before n (SINK reads the row
+    #    numbers from the quarantine; under REPORT they lie in the unregistered padding after I
+    #    and read as 0)
+    i_end = off["I"][1]
+    Iend = ar.addr(i_end - 8 * (n - 100))
+    ar.write(i_end - 8 * (n - 100), rng.integers(0, ROWS, n - 100).astype(np.int64))
+    run_both(tw, ar, lambda: g.agile_guarded_gather(tw.h, C, A, rb, Iend, n, 0 if w == 4 else 1,
+                                                    policy),
+             lambda: G.gather_loop(tw.ot, ar.mem, ol, tw.next_seq(), C, A, rb, Iend, n, w,
+                                   policy, quarantine=quar), ol, "gather, denied index loads")
+    # 3. denied output stores: the output runs 50 rows past C's end (into the next buffer)
+    ar.write(off["I"][0], rng.integers(0, ROWS, n).astype(np.int64))
+    Cend = ar.addr(off["C"][1] - rb * (n - 50))
+    run_both(tw, ar, lambda: g.agile_guarded_gather(tw.h, Cend, A, rb, I, n, 0 if w == 4 else 1,
+                                                    policy),
+             lambda: G.gather_loop(tw.ot, ar.mem, ol, tw.next_seq(), Cend, A, rb, I, n, w,
+                                   policy, quarantine=quar), ol, "gather, denied stores")
+    # 4. scatter with destination rows past the end of A (distinct rows: stores only). Under
+    #    SINK they stay within 4 KiB (P), so that no two of them share a quarantine slot.
+    idx = rng.permutation(ROWS)[:n].astype(np.int64)
+    past_st = [r for r in past if (r - ROWS) * rb < 4096] if policy == G.SINK else past
+    pos = rng.choice(n, len(past_st), replace=False)
+    idx[pos] = past_st
+    ar.write(off["I"][0], idx)
+    run_both(tw, ar, lambda: g.agile_guarded_scatter(tw.h, A, rb, I, S, n, 0 if w == 4 else 1, 0,
+                                                     policy),
+             lambda: G.scatter_loop(tw.ot, ar.mem, ol, tw.next_seq(), A, rb, I, S, n, w, False,
+                                    policy, quarantine=quar), ol, "scatter")
+    tw.close()
+
+
+@pytest.mark.parametrize("policy", [G.SINK, G.REPORT])
+@pytest.mark.parametrize("n", [600, NMAX])
+def test_scatter_add_redirected(policy, n):
+    """Duplicate destination rows, rows past the end (into P, H, X) and before it, and a
+    source that runs out 30 rows early; NMAX rows take the sorted path."""
+    w, D = 4, 2
+    ar, tw, off, dt, rng = setup(w, D, 50 + n + policy)
+    g = tw.g
+    rb = w * D
+    A, I, S, Q = (ar.addr(off[k][0]) for k in ("A", "I", "S", "Q"))
+    ol = G.FaultLog()
+    ar.write(off["Q"][0], np.zeros(QSIZE // 4, np.float32))
+    idx = rng.integers(0, 64, n).astype(np.int64)
+    bad = rng.choice(n, 200, replace=False)
+    # quarantine slots of these rows (A + 8 r mod 4096: 0, 24, 3200, 3808, 4088, 4040) stay
+    # clear of those of the source's denied loads (S's end + 8 k: 512 .. 752)
+    idx[bad] = rng.choice([ROWS, ROWS + 3, ROWS + 400, ROWS + 1500, -1, -7], 200)
+    ar.write(off["I"][0], idx)
+    Send = ar.addr(off["S"][1] - rb * (n - 30))
+    run_both(tw, ar, lambda: g.agile_guarded_scatter(tw.h, A, rb, I, Send, n, 0, 1, policy),
+             lambda: G.scatter_loop(tw.ot, ar.mem, ol, tw.next_seq(), A, rb, I, Send, n, w, True,
+                                    policy, quarantine=(Q, QSIZE)), ol, f"scatter-add n={n}")
+    tw.close()
+
+
+@pytest.mark.parametrize("policy", [G.SINK, G.REPORT])
+def test_copy_and_triad_redirected(policy):
+    w, D = 4, 1
+    ar, tw, off, dt, rng = setup(w, D, 70 + policy)
+    g = tw.g
+    A, X, C, Q = (ar.addr(off[k][0]) for k in ("A", "X", "C", "Q"))
+    quar = (Q, QSIZE)
+    ar.write(off["Q"][0], rng.integers(-20, 21, QSIZE // 4).astype(np.float32))
+    ol = G.FaultLog()
+    a_end = off["A"][1]
+    # copy: the source runs 1000 bytes past A into P (loads), then the destination runs 1000
+    # bytes past A (stores)
+    src = ar.addr(a_end - 3000)
+    run_both(tw, ar, lambda: g.agile_guarded_copy(tw.h, C, src, 4000, policy),
+             lambda: G.copy_loop(tw.ot, ar.mem, ol, tw.next_seq(), C, src, 4000, policy,
+                                 quarantine=quar), ol, "copy, denied loads")
+    run_both(tw, ar, lambda: g.agile_guarded_copy(tw.h, src, C, 4000, policy),
+             lambda: G.copy_loop(tw.ot, ar.mem, ol, tw.next_seq(), src, C, 4000, policy,
+                                 quarantine=quar), ol, "copy, denied stores")
+    # triad: b runs 200 elements past A, then a runs 200 elements past A
+    bb = ar.addr(a_end - 4 * 300)
+    run_both(tw, ar, lambda: g.agile_guarded_triad(tw.h, C, bb, X, 2.0, 500, policy),
+             lambda: G.triad_loop(tw.ot, ar.mem, ol, tw.next_seq(), C, bb, X, 2.0, 500, policy,
+                                  quarantine=quar), ol, "triad, denied loads")
+    run_both(tw, ar, lambda: g.agile_guarded_triad(tw.h, bb, C, X, 2.0, 500, policy),
+             lambda: G.triad_loop(tw.ot, ar.mem, ol, tw.next_seq(), bb, C, X, 2.0, 500, policy,
+                                  quarantine=quar), ol, "triad, denied stores")
+    tw.close()
+
+
+def test_sink_without_quarantine_is_refused():
+    need_gpu()
+    tw = Twin(4)
+    g = tw.g
+    g.agile_rt_set_quarantine(tw.h, 0, 0)
+    with pytest.raises(g.AgileError) as e:
+        g.agile_guarded_copy(tw.h, 0, 0, 16, G.SINK)
+    assert e.value.code == g.AGILE_EINVAL
+    for bad in ((1 << 20, 300), (1 << 20, 4096 + 256), ((1 << 20) + 8, 4096)):
+        with pytest.raises(g.AgileError):
+            g.agile_rt_set_quarantine(tw.h, *bad)
+    tw.close()
