@@ -6,8 +6,8 @@
  * module and MMIO ranges (Section IV-E, Table I; Section V-A records each allocation's base
  * and live size), batched API-time pointer validation and the DMA registration check
  * (Section IV-E, V-C), and guarded kernels whose every global access is checked before it
- * happens, with the paper's poison (record, fail later), sink (to a zero page) and trap
- * (retire) policies (Section V-E). Around them: client handle tokens (Section IV-C), a batched
+ * happens, with the paper's poison (record, fail later), sink (to a zero page or a
+ * quarantine), report and trap (retire) policies (Section V-E). Around them: client handle tokens (Section IV-C), a batched
  * multi-client launch and a native serving loop with revocation (Sections IV-B, IV-D).
  *
  * Conventions for every entry point
