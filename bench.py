@@ -175,6 +175,18 @@ def main():
     ok_triad = torch.equal(a.view(torch.int32), a_ref.view(torch.int32))
     good = (idx >= 0) & (idx < GATHER_ROWS)
     ok_gather = bool(torch.equal(out[good], out_ref[good])) and bool((out[~good] == 0).all())
+    # the redirecting policies on the same gather (the guarded kernel, then the redirect pass)
+    qbuf = torch.zeros(1 << 16, dtype=torch.uint8, device=dev)
+    g.agile_rt_set_quarantine(dt.handle, qbuf, 1 << 16)
+    pol = time_blocks({
+        "gather_sink": lambda: g.agile_guarded_gather(dt.handle, out, table, 4, idx, GATHER_N, 0,
+                                                      g.POLICY_SINK),
+        "gather_report": lambda: g.agile_guarded_gather(dt.handle, out, table, 4, idx, GATHER_N,
+                                                        0, g.POLICY_REPORT),
+    }, args.warmup, args.steps)
+    dt.fault_log(clear=True)
+    g.agile_rt_set_quarantine(dt.handle, 0, 0)
+    torch.cuda.synchronize()
 
     def med(x):
         return float(np.median(np.array(x)))
@@ -219,6 +231,8 @@ def main():
         "kernel_ms": {"validate": round(t_v, 4), "validate_dma": round(med(twin["validate_dma"]), 4),
                       "triad": round(t_t, 4),
                       "gather": round(t_g, 4), "triad_unguarded": round(ug_t, 4),
+                      "gather_sink": round(med(pol["gather_sink"]), 4),
+                      "gather_report": round(med(pol["gather_report"]), 4),
                       "gather_unguarded": round(ug_g, 4)},
         "guarded_gbps": {k: round(v, 1) for k, v in gbs.items()},
         "unguarded_gbps": {k: round(v, 1) for k, v in ugbs.items()},
@@ -236,7 +250,7 @@ def main():
                      "bytes_per_launch": per_launch[dominant]},
     }
     result["roofline"]["traffic"] = measured_traffic(dominant, per_launch[dominant])
-    del q, verdict, owner, a, b, c, a_ref, gbuf, table, idx, out, out_ref
+    del q, verdict, owner, a, b, c, a_ref, gbuf, table, idx, out, out_ref, qbuf
     vt.close()
     dt.close()
     torch.cuda.empty_cache()
