@@ -29,8 +29,13 @@ access is redirected to a caller-provided quarantine of ``qsize`` bytes (a power
 rounded down to a multiple of ``w`` (loads read it, stores write it, scatter-add adds into
 it). Under ``REPORT`` a denied access is performed at ``A`` itself when ``[A, A+w)`` lies inside
 one registered range of any kind (memory the table vouches for), and suppressed otherwise
-(memory outside every range may not be mapped). Both log every denial like ``SUPPRESS_LOG``.
-Only the per-access loops define them. The paper's ``trap`` stops at a violation and
+(memory outside every range may not be mapped). Under ``REMAP`` (the paper's ``remap_or``,
+kept to the condition under which the paper calls it safe: the target is a live user
+allocation) a denied access is rewritten into its own argument's allocation ``[lo, hi)``:
+with ``lo'`` = lo rounded up to a multiple of ``w`` and ``m`` the largest multiple of ``w``
+not above ``hi - lo'``, it goes to ``lo' + ((A - lo') mod m)`` rounded down to a multiple of
+``w``; an argument without a binding (or with ``m == 0``) leaves it suppressed. All three log
+every denial like ``SUPPRESS_LOG``. Only the per-access loops define them. The paper's ``trap`` stops at a violation and
 may leave the worker's context unusable, so the worker is retired (Section V-E; Section IV-D,
 lifetime and revocation). Restated per call (``guarded_call``): a call of a retired handle does
 nothing and reports ``ETRAPPED``; a ``TRAP`` call runs as under ``SUPPRESS_LOG`` (the denied
@@ -54,7 +59,8 @@ import numpy as np
 from .table import ALLOW, V_CROSS_ALLOC, V_UNMAPPED, U64_MAX
 
 OP_COPY, OP_TRIAD, OP_GATHER, OP_SCATTER, OP_SCATTER_ADD = 1, 2, 3, 4, 5
-SUPPRESS_LOG, SUPPRESS_ONLY, TRAP, SINK, REPORT = 0, 1, 2, 3, 4
+SUPPRESS_LOG, SUPPRESS_ONLY, TRAP, SINK, REPORT, REMAP = 0, 1, 2, 3, 4, 5
+REDIRECTING = (SINK, REPORT, REMAP)
 OK, ETRAPPED = 0, -8
 _DT = {4: np.float32, 8: np.float64}
 
@@ -101,9 +107,9 @@ def _allowed(bind, A, w):
 
 class _Denier:
     def __init__(self, table, log, seq, op, policy, quarantine=None, loops=True):
-        if policy not in (SUPPRESS_LOG, SUPPRESS_ONLY, TRAP, SINK, REPORT):
+        if policy not in (SUPPRESS_LOG, SUPPRESS_ONLY, TRAP) + REDIRECTING:
             raise ValueError("unknown policy")
-        if policy in (SINK, REPORT) and not loops:
+        if policy in REDIRECTING and not loops:
             raise NotImplementedError("the redirecting policies are defined by the loop forms")
         if policy == SINK:
             qb, qs = quarantine
@@ -117,8 +123,18 @@ class _Denier:
         if self.on:
             self.log.offer(self.t, self.seq, elem, operand, A, w, self.op)
 
-    def target(self, A, w):
-        """Where a denied access of width w at exact address A goes (None: suppressed)."""
+    def target(self, A, w, bind=(0, 0)):
+        """Where a denied access of width w at exact address A of the argument bound to
+        ``bind`` goes (None: suppressed)."""
+        if self.policy == REMAP:
+            lo, hi = bind
+            if hi <= lo:
+                return None
+            lo_a = -(-lo // w) * w
+            m = (hi - lo_a) // w * w
+            if m <= 0:
+                return None
+            return lo_a + ((A - lo_a) % m) // w * w
         if self.policy == SINK:
             qb, qs = self.q
             return qb + ((A % (1 << 64)) % qs) // w * w
@@ -130,18 +146,18 @@ class _Denier:
                 return A
         return None
 
-    def load(self, mem, A, w):
+    def load(self, mem, A, w, bind=(0, 0)):
         """The bytes a denied load reads."""
-        t = self.target(A, w)
+        t = self.target(A, w, bind)
         return bytes(w) if t is None else mem.read(t, w)
 
-    def store(self, mem, A, data):
-        t = self.target(A, len(data))
+    def store(self, mem, A, data, bind=(0, 0)):
+        t = self.target(A, len(data), bind)
         if t is not None:
             mem.write(t, data)
 
-    def add(self, mem, A, val, dt):
-        t = self.target(A, dt().itemsize)
+    def add(self, mem, A, val, dt, bind=(0, 0)):
+        t = self.target(A, dt().itemsize, bind)
         if t is not None:
             old = np.frombuffer(mem.read(t, dt().itemsize), dtype=dt)[0]
             mem.write(t, dt(old + val).tobytes())
@@ -172,13 +188,13 @@ def copy_loop(table, mem, log, seq, dst, src, n, policy=SUPPRESS_LOG, quarantine
         if _allowed(bs, A, 1):
             byte = mem.read(A, 1)
         else:
-            byte = deny.load(mem, A, 1)
+            byte = deny.load(mem, A, 1, bs)
             deny(k, 0, A, 1)
         A = dst + k
         if _allowed(bd, A, 1):
             mem.write(A, byte)
         else:
-            deny.store(mem, A, byte)
+            deny.store(mem, A, byte, bd)
             deny(k, 1, A, 1)
 
 
@@ -197,7 +213,7 @@ def triad_loop(table, mem, log, seq, a, b, c, s, n, policy=SUPPRESS_LOG, quarant
             if _allowed(bind, A, 4):
                 vals.append(_f32(mem.read(A, 4)))
             else:
-                vals.append(_f32(deny.load(mem, A, 4)))
+                vals.append(_f32(deny.load(mem, A, 4, bind)))
                 deny(i, op_i, A, 4)
         prod = np.float32(s32 * vals[1])          # first rounding
         r = np.float32(vals[0] + prod)            # second rounding
@@ -205,7 +221,7 @@ def triad_loop(table, mem, log, seq, a, b, c, s, n, policy=SUPPRESS_LOG, quarant
         if _allowed(ba, A, 4):
             mem.write(A, np.float32(r).tobytes())
         else:
-            deny.store(mem, A, np.float32(r).tobytes())
+            deny.store(mem, A, np.float32(r).tobytes(), ba)
             deny(i, 2, A, 4)
 
 
@@ -214,7 +230,7 @@ def _idx_load(mem, bind, idx_ptr, i, deny, elem):
     if _allowed(bind, A, 8):
         return int(np.frombuffer(mem.read(A, 8), dtype=np.int64)[0])
     deny(elem, 0, A, 8)
-    return int(np.frombuffer(deny.load(mem, A, 8), dtype=np.int64)[0])
+    return int(np.frombuffer(deny.load(mem, A, 8, bind), dtype=np.int64)[0])
 
 
 def gather_loop(table, mem, log, seq, out, T, row_bytes, idx_ptr, n, w=4,
@@ -230,13 +246,13 @@ def gather_loop(table, mem, log, seq, out, T, row_bytes, idx_ptr, n, w=4,
             if _allowed(bt, A, w):
                 val = mem.read(A, w)
             else:
-                val = deny.load(mem, A, w)
+                val = deny.load(mem, A, w, bt)
                 deny(e, 1, A, w)
             A = out + i * row_bytes + col * w
             if _allowed(bo, A, w):
                 mem.write(A, val)
             else:
-                deny.store(mem, A, val)
+                deny.store(mem, A, val, bo)
                 deny(e, 2, A, w)
 
 
@@ -255,7 +271,7 @@ def scatter_loop(table, mem, log, seq, dst, row_bytes, idx_ptr, src, n, w=4, acc
             if _allowed(bs, A, w):
                 val = mem.read(A, w)
             else:
-                val = deny.load(mem, A, w)
+                val = deny.load(mem, A, w, bs)
                 deny(e, 1, A, w)
             A = dst + iv * row_bytes + col * w
             if _allowed(bd, A, w):
@@ -267,9 +283,9 @@ def scatter_loop(table, mem, log, seq, dst, row_bytes, idx_ptr, src, n, w=4, acc
                     mem.write(A, val)
             else:
                 if accumulate:
-                    deny.add(mem, A, np.frombuffer(val, dtype=dt)[0], dt)
+                    deny.add(mem, A, np.frombuffer(val, dtype=dt)[0], dt, bd)
                 else:
-                    deny.store(mem, A, val)
+                    deny.store(mem, A, val, bd)
                 deny(e, 2, A, w)
 
 

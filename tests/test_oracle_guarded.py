@@ -490,7 +490,7 @@ def test_redirecting_policies_log_like_suppress_for_copy_and_triad(seed):
             continue
         ref = RecordingLog()
         G.copy_loop(t, copy.deepcopy(mem), ref, trial, dst, src, n)
-        for pol in (G.SINK, G.REPORT):
+        for pol in G.REDIRECTING:
             m = copy.deepcopy(mem)
             q = _with_quarantine(m, 7)
             log = G.FaultLog()
@@ -500,7 +500,7 @@ def test_redirecting_policies_log_like_suppress_for_copy_and_triad(seed):
             continue
         ref = RecordingLog()
         G.triad_loop(t, copy.deepcopy(mem), ref, trial, dst, src, c, 2.0, n)
-        for pol in (G.SINK, G.REPORT):
+        for pol in G.REDIRECTING:
             m = copy.deepcopy(mem)
             log = G.FaultLog()
             G.triad_loop(t, m, log, trial, dst, src, c, 2.0, n, pol,
@@ -611,3 +611,48 @@ def test_sink_scatter_add_accumulates_in_the_quarantine():
     quar = np.frombuffer(mem.read(Q_BASE, Q_SIZE), np.float32)
     # row 4 -> BASE + 16 (slot 16 / 4 = 4), row 9 -> BASE + 36 (slot 9)
     assert quar[4] == 5.0 and quar[9] == 4.0 and quar.sum() == 9.0
+
+
+def test_remap_copy_from_a_short_allocation_repeats_it():
+    """A copy of 1000 bytes from a 37-byte allocation under REMAP reads byte k at k mod 37:
+    numpy's tiled repetition of the source."""
+    t, mem = RangeTable(), Memory()
+    src = np.arange(37, dtype=np.uint8) * 3
+    t.insert(BASE + 3, 37, USER)
+    mem.add(BASE + 3, src)
+    t.insert(BASE + 0x1000, 1000, USER)
+    mem.add(BASE + 0x1000, np.zeros(1000, np.uint8))
+    log = G.FaultLog()
+    G.copy_loop(t, mem, log, 0, BASE + 0x1000, BASE + 3, 1000, G.REMAP)
+    assert mem.read(BASE + 0x1000, 1000) == np.resize(src, 1000).tobytes()
+    assert log.count == 1000 - 37
+
+
+@pytest.mark.parametrize("D", [1, 3])
+def test_remap_gather_wraps_rows_like_take(D):
+    """A table allocation of rows*rb + 2 bytes: REMAP wraps whole elements, so every index
+    (past the end or negative) reads row idx mod rows, as np.take(..., mode='wrap')."""
+    rng = np.random.default_rng(D)
+    rows, n = 37, 200
+    W = rng.integers(-50, 50, (rows, D)).astype(np.float32)
+    idx = rng.integers(-500, 500, n).astype(np.int64)
+    t, mem = RangeTable(), Memory()
+    t.insert(BASE, W.nbytes + 2, USER)
+    mem.add(BASE, np.concatenate([W.view(np.uint8).reshape(-1), np.zeros(2, np.uint8)]))
+    t.insert(BASE + (1 << 20), idx.nbytes, USER)
+    mem.add(BASE + (1 << 20), idx.view(np.uint8))
+    t.insert(BASE + (2 << 20), n * D * 4, USER)
+    mem.add(BASE + (2 << 20), np.zeros(n * D * 4, np.uint8))
+    G.gather_loop(t, mem, G.FaultLog(), 0, BASE + (2 << 20), BASE, 4 * D, BASE + (1 << 20), n,
+                  4, G.REMAP)
+    got = np.frombuffer(mem.read(BASE + (2 << 20), n * D * 4), np.float32).reshape(n, D)
+    assert np.array_equal(got, np.take(W, idx, axis=0, mode="wrap"))
+
+
+def test_remap_without_a_binding_suppresses():
+    t, mem, addr = scenario(7)
+    m1, m2 = copy.deepcopy(mem), copy.deepcopy(mem)
+    G.copy_loop(t, m1, G.FaultLog(), 0, addr["P"][0], addr["A"][0], 64, G.REMAP)
+    G.copy_loop(t, m2, G.FaultLog(), 0, addr["P"][0], addr["A"][0], 64)
+    _same(m1, m2, addr)
+    assert m1.read(addr["P"][0], 64) == bytes([0xA5] * 64)

@@ -44,7 +44,11 @@ GUARD_CHECKS = ([PG.test_access_straddling_the_allocation_end_is_denied,
                  PG.test_sink_aligns_the_slot_to_the_access_width,
                  PG.test_report_performs_only_inside_registered_ranges,
                  PG.test_sink_with_a_zero_quarantine_and_no_denied_store_equals_suppress,
-                 PG.test_sink_scatter_add_accumulates_in_the_quarantine] +
+                 PG.test_sink_scatter_add_accumulates_in_the_quarantine,
+                 PG.test_remap_copy_from_a_short_allocation_repeats_it,
+                 lambda: PG.test_remap_gather_wraps_rows_like_take(1),
+                 lambda: PG.test_remap_gather_wraps_rows_like_take(3),
+                 PG.test_remap_without_a_binding_suppresses] +
                 [lambda s=s: PG.test_redirecting_policies_log_like_suppress_for_copy_and_triad(s)
                  for s in range(4)] +
                 [lambda s=s: PG.test_copy_vec_matches_loop(s) for s in range(6)] +
@@ -202,25 +206,32 @@ def _trapping_call_rolled_back(orig):
     return guarded_call
 
 
-def _target_unaligned(self, A, w):
+def _target_unaligned(self, A, w, bind=(0, 0)):
     if self.policy == G.SINK:
         qb, qs = self.q
         return qb + (A % (1 << 64)) % qs
-    return _ORIG_TARGET(self, A, w)
+    return _ORIG_TARGET(self, A, w, bind)
 
 
-def _target_report_everywhere(self, A, w):
+def _target_report_everywhere(self, A, w, bind=(0, 0)):
     if self.policy == G.REPORT:
         return A
-    return _ORIG_TARGET(self, A, w)
+    return _ORIG_TARGET(self, A, w, bind)
 
 
-def _store_dropped(self, mem, A, data):
+def _target_remap_by_size(self, A, w, bind=(0, 0)):
+    if self.policy == G.REMAP and bind[1] > bind[0]:
+        lo, hi = bind
+        return lo + ((A - lo) % (hi - lo)) // w * w
+    return _ORIG_TARGET(self, A, w, bind)
+
+
+def _store_dropped(self, mem, A, data, bind=(0, 0)):
     return None
 
 
-def _add_overwrites(self, mem, A, val, dt):
-    t = self.target(A, dt().itemsize)
+def _add_overwrites(self, mem, A, val, dt, bind=(0, 0)):
+    t = self.target(A, dt().itemsize, bind)
     if t is not None:
         mem.write(t, dt(val).tobytes())
 
@@ -230,6 +241,7 @@ _ORIG_TARGET = G._Denier.target
 DENIER_MUTANTS = {
     "sink slot not aligned to the access width": ("target", _target_unaligned),
     "report performs outside registered ranges": ("target", _target_report_everywhere),
+    "remap wraps by the allocation size, not whole elements": ("target", _target_remap_by_size),
     "redirected stores dropped": ("store", _store_dropped),
     "redirected scatter-add overwrites": ("add", _add_overwrites),
 }
