@@ -90,7 +90,8 @@ enum {
     AGILE_POLICY_SUPPRESS_ONLY = 1,
     AGILE_POLICY_TRAP = 2,
     AGILE_POLICY_SINK = 3,
-    AGILE_POLICY_REPORT = 4
+    AGILE_POLICY_REPORT = 4,
+    AGILE_POLICY_REMAP = 5
 };
 /* SINK (Section V-E "sink": redirect to quarantine memory, for debugging, without isolation
  * between violations): a denied access of width w at exact address A goes to the handle's
@@ -102,7 +103,14 @@ enum {
  * Both log every denial as SUPPRESS_LOG does, and both run a second pass after the guarded
  * kernel on the same stream. Denied accesses of one call that reach the same quarantine slot
  * or address are unordered (like duplicate indices of a plain scatter). SINK without a
- * quarantine is EINVAL. */
+ * quarantine is EINVAL.
+ * REMAP (Section V-E "remap_or", restricted to a safe target): a denied access of width w at
+ * exact address A through a pointer argument whose USER range is [lo, hi) is rewritten into
+ * that range: with lo' = lo rounded up to a multiple of w and m the largest multiple of w not
+ * above hi - lo', it goes to lo' + ((A - lo') mod m) rounded down to a multiple of w (mod taken
+ * non-negative). A pointer with no USER range (or with m == 0) leaves the access suppressed.
+ * It is logged and run like SINK and REPORT; a remapped store can overwrite data that other
+ * elements of the same call read or write, in no defined order. */
 
 /* Guarded operations, as recorded in a fault record. */
 enum {

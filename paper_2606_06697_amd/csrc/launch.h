@@ -60,23 +60,30 @@ constexpr uint64_t SORT_MIN_N = 1u << 15;
 hipError_t launch_log_reset(DevLog* log, hipStream_t s);
 
 // Redirecting policies (sink to a quarantine, report): the pass after a guarded kernel.
-constexpr uint32_t REDIRECT_SINK = 1, REDIRECT_REPORT = 2;
+constexpr uint32_t REDIRECT_SINK = 1, REDIRECT_REPORT = 2, REDIRECT_REMAP = 3;
 struct Redirect {
     uint32_t mode;
     uint32_t pad;
     uint8_t* q;      // quarantine (SINK)
     uint64_t qmask;  // its size - 1 (a power of two)
 };
-hipError_t launch_copy_fix(const DevTable& t, const Redirect& r, void* dst, const void* src,
-                           uint64_t n, uint64_t Ks, uint64_t Kd, const DevInfo& d, hipStream_t s);
-hipError_t launch_triad_fix(const DevTable& t, const Redirect& r, float* a, const float* b,
-                            const float* c, float sc, uint64_t n, uint64_t Ka, uint64_t Kb,
-                            uint64_t Kc, const DevInfo& d, hipStream_t s);
+// The bindings (REMAP rewrites into them) come in operand order.
+struct RowBinds {
+    Bind idx, cont, row;  // index array, contiguous operand (out / src), row-addressed operand
+};
+hipError_t launch_copy_fix(const DevTable& t, const Redirect& r, Bind bs, Bind bd, void* dst,
+                           const void* src, uint64_t n, uint64_t Ks, uint64_t Kd, const DevInfo& d,
+                           hipStream_t s);
+hipError_t launch_triad_fix(const DevTable& t, const Redirect& r, Bind ba, Bind bb, Bind bc,
+                            float* a, const float* b, const float* c, float sc, uint64_t n,
+                            uint64_t Ka, uint64_t Kb, uint64_t Kc, const DevInfo& d,
+                            hipStream_t s);
 // op 0 gather (cont = out, rowp = table), 1 scatter, 2 scatter-add (cont = src, rowp = dst);
 // rg: the guard over all n rows; the guarded kernel ran rows below rg.ki.
-hipError_t launch_rows_fix(int op, const DevTable& t, DevLog* log, const Redirect& r, void* cont,
-                           void* rowp, uint64_t rb, const int64_t* idx, uint64_t n,
-                           const RowsGuard& rg, uint32_t w, const DevInfo& d, hipStream_t s);
+hipError_t launch_rows_fix(int op, const DevTable& t, DevLog* log, const Redirect& r,
+                           const RowBinds& bb, void* cont, void* rowp, uint64_t rb,
+                           const int64_t* idx, uint64_t n, const RowsGuard& rg, uint32_t w,
+                           const DevInfo& d, hipStream_t s);
 
 // After a guarded row kernel: folds the launch's denial count into the log and records the
 // smallest key if the log is empty.

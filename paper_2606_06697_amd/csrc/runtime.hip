@@ -588,14 +588,15 @@ int agile_validate_dma(agile_rt* rt, const agile_ptr* d_q, uint64_t n, uint8_t* 
 static bool policy_ok(int policy) {
     return policy == AGILE_POLICY_SUPPRESS_LOG || policy == AGILE_POLICY_SUPPRESS_ONLY ||
            policy == AGILE_POLICY_TRAP || policy == AGILE_POLICY_SINK ||
-           policy == AGILE_POLICY_REPORT;
+           policy == AGILE_POLICY_REPORT || policy == AGILE_POLICY_REMAP;
 }
 
 static bool redirecting(int policy) {
-    return policy == AGILE_POLICY_SINK || policy == AGILE_POLICY_REPORT;
+    return policy == AGILE_POLICY_SINK || policy == AGILE_POLICY_REPORT ||
+           policy == AGILE_POLICY_REMAP;
 }
 
-// The redirect of a SINK or REPORT call (EINVAL: SINK without a quarantine).
+// The redirect of a SINK, REPORT or REMAP call (EINVAL: SINK without a quarantine).
 static int redirect_of(const agile_rt* rt, int policy, Redirect* r) {
     *r = Redirect{};
     if (policy == AGILE_POLICY_SINK) {
@@ -604,7 +605,7 @@ static int redirect_of(const agile_rt* rt, int policy, Redirect* r) {
         r->q = rt->q_ptr;
         r->qmask = rt->q_bytes - 1;
     } else {
-        r->mode = REDIRECT_REPORT;
+        r->mode = policy == AGILE_POLICY_REMAP ? REDIRECT_REMAP : REDIRECT_REPORT;
     }
     return AGILE_OK;
 }
@@ -685,7 +686,7 @@ int agile_guarded_copy(agile_rt* rt, void* d_dst, const void* d_src, uint64_t nb
                     log_on(policy), rt->info, s) != hipSuccess)
         return AGILE_EDEVICE;
     if (redirecting(policy) &&
-        launch_copy_fix(rt->tab, rd, d_dst, d_src, nbytes,
+        launch_copy_fix(rt->tab, rd, b[0], b[1], d_dst, d_src, nbytes,
                         clip_prefix(b[0], (uint64_t)d_src, nbytes, 1),
                         clip_prefix(b[1], (uint64_t)d_dst, nbytes, 1), rt->info, s) != hipSuccess)
         return AGILE_EDEVICE;
@@ -714,7 +715,8 @@ int agile_guarded_triad(agile_rt* rt, float* d_a, const float* d_b, const float*
                      log_on(policy), rt->info, s) != hipSuccess)
         return AGILE_EDEVICE;
     if (redirecting(policy) &&
-        launch_triad_fix(rt->tab, rd, d_a, d_b, d_c, s_, n, clip_prefix(b[2], (uint64_t)d_a, n, 4),
+        launch_triad_fix(rt->tab, rd, b[2], b[0], b[1], d_a, d_b, d_c, s_, n,
+                         clip_prefix(b[2], (uint64_t)d_a, n, 4),
                          clip_prefix(b[0], (uint64_t)d_b, n, 4),
                          clip_prefix(b[1], (uint64_t)d_c, n, 4), rt->info, s) != hipSuccess)
         return AGILE_EDEVICE;
@@ -758,7 +760,8 @@ int agile_guarded_gather(agile_rt* rt, void* d_out, const void* d_table, uint64_
                                           (uint64_t)d_table, n, row_bytes, w);
         if (launch_gather(true, rt->tab, rt->d_log, b, d_out, d_table, row_bytes, d_idx, full.ki,
                           w, seq, 1, rt->info, s, false) != hipSuccess ||
-            launch_rows_fix(0, rt->tab, rt->d_log, rd, d_out, const_cast<void*>(d_table),
+            launch_rows_fix(0, rt->tab, rt->d_log, rd, RowBinds{b[0], b[2], b[1]}, d_out,
+                            const_cast<void*>(d_table),
                             row_bytes, d_idx, n, full, w, rt->info, s) != hipSuccess ||
             launch_fault_finish(rt->tab, rt->d_log,
                                 rows_fault_site(AGILE_OP_GATHER, w, 1, row_bytes, full.ki, d_idx,
@@ -801,8 +804,9 @@ int agile_guarded_scatter(agile_rt* rt, void* d_dst, uint64_t row_bytes, const i
                                           (uint64_t)d_dst, n, row_bytes, w);
         if (launch_scatter(true, rt->tab, rt->d_log, b, d_dst, row_bytes, d_idx, d_src, full.ki, w,
                            accumulate, seq, 1, scr, rt->info, s, false) != hipSuccess ||
-            launch_rows_fix(accumulate ? 2 : 1, rt->tab, rt->d_log, rd, const_cast<void*>(d_src),
-                            d_dst, row_bytes, d_idx, n, full, w, rt->info, s) != hipSuccess ||
+            launch_rows_fix(accumulate ? 2 : 1, rt->tab, rt->d_log, rd,
+                            RowBinds{b[0], b[1], b[2]}, const_cast<void*>(d_src), d_dst,
+                            row_bytes, d_idx, n, full, w, rt->info, s) != hipSuccess ||
             launch_fault_finish(rt->tab, rt->d_log,
                                 rows_fault_site(accumulate ? AGILE_OP_SCATTER_ADD : AGILE_OP_SCATTER,
                                                 w, 2, row_bytes, full.ki, d_idx, d_src, d_dst),

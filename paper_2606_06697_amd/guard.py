@@ -22,7 +22,8 @@ AGILE_ENOENT, AGILE_ENOSPC, AGILE_EDEVICE, AGILE_EFAULTED = -4, -5, -6, -7
 AGILE_ETRAPPED = -8
 KIND_USER, KIND_PROTECTED, KIND_MMIO = 0, 1, 2
 ALLOW, V_PROTECTED, V_STRADDLE, V_UNMAPPED, V_CROSS_ALLOC, V_INEXACT = 0, 1, 2, 3, 4, 5
-POLICY_SUPPRESS_LOG, POLICY_SUPPRESS_ONLY, POLICY_TRAP, POLICY_SINK, POLICY_REPORT = 0, 1, 2, 3, 4
+(POLICY_SUPPRESS_LOG, POLICY_SUPPRESS_ONLY, POLICY_TRAP, POLICY_SINK, POLICY_REPORT,
+ POLICY_REMAP) = 0, 1, 2, 3, 4, 5
 OP_COPY, OP_TRIAD, OP_GATHER, OP_SCATTER, OP_SCATTER_ADD = 1, 2, 3, 4, 5
 DTYPE_F32, DTYPE_F64 = 0, 1
 TOKEN_VALID, TOKEN_FORGED, TOKEN_STALE, TOKEN_CROSS_CLIENT, TOKEN_WRONG_KIND = 0, 1, 2, 3, 4

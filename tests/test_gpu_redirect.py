@@ -2,14 +2,18 @@
 
 SINK sends every denied access to a caller-provided quarantine (slot = address mod its size,
 rounded down to the width); REPORT performs a denied access when it lies inside a registered
-range of any kind and suppresses it otherwise (Section V-E, sink and report). One arena holds:
+range of any kind and suppresses it otherwise; REMAP rewrites it into the USER range of its own
+pointer argument, modulo that range's size (Section V-E, sink, report and remap_or). One arena
+holds:
 a USER table/destination A, a protected canary P, an unregistered hole H, another USER
 allocation X, an index buffer I, a source S, an output C and the quarantine Q (not
 registered). Every registered range is backed by the arena, so REPORT only ever touches arena
 bytes. Values are small integers, so sums are exact in any order, and the whole arena,
 quarantine included, must equal the oracle's memory byte for byte. Within one call the denied
 accesses that reach the same quarantine slot or address are either all loads or all adds
-(their order is unspecified, as for duplicate indices of a plain scatter).
+(their order is unspecified, as for duplicate indices of a plain scatter); under REMAP the
+layouts keep rewritten stores off every address that an allowed access of the same call reads
+or writes.
 """
 import numpy as np
 import pytest
@@ -59,7 +63,7 @@ def run_both(tw, ar, fn_dev, fn_or, ol, what):
     log_matches(tw, ol, what)
 
 
-@pytest.mark.parametrize("policy", [G.SINK, G.REPORT])
+@pytest.mark.parametrize("policy", [G.SINK, G.REPORT, G.REMAP])
 @pytest.mark.parametrize("w,D", [(4, 1), (4, 4), (8, 2)])
 def test_gather_and_scatter_redirected(policy, w, D):
     ar, tw, off, dt, rng = setup(w, D, 11 + w + D + policy)
@@ -102,9 +106,15 @@ def test_gather_and_scatter_redirected(policy, w, D):
              lambda: G.gather_loop(tw.ot, ar.mem, ol, tw.next_seq(), Cend, A, rb, I, n, w,
                                    policy, quarantine=quar), ol, "gather, denied stores")
     # 4. scatter with destination rows past the end of A (distinct rows: stores only). Under
-    #    SINK they stay within 4 KiB (P), so that no two of them share a quarantine slot.
+    #    SINK they stay within 4 KiB (P), so that no two of them share a quarantine slot; under
+    #    REMAP (row r goes to row r mod ROWS) the allowed rows avoid every rewritten one.
     idx = rng.permutation(ROWS)[:n].astype(np.int64)
     past_st = [r for r in past if (r - ROWS) * rb < 4096] if policy == G.SINK else past
+    if policy == G.REMAP:
+        past_st = past[::5]
+        hit = {r % ROWS for r in past_st}
+        assert len(hit) == len(past_st)
+        idx = rng.permutation([r for r in range(ROWS) if r not in hit])[:n].astype(np.int64)
     pos = rng.choice(n, len(past_st), replace=False)
     idx[pos] = past_st
     ar.write(off["I"][0], idx)
@@ -115,7 +125,7 @@ def test_gather_and_scatter_redirected(policy, w, D):
     tw.close()
 
 
-@pytest.mark.parametrize("policy", [G.SINK, G.REPORT])
+@pytest.mark.parametrize("policy", [G.SINK, G.REPORT, G.REMAP])
 @pytest.mark.parametrize("n", [600, NMAX])
 def test_scatter_add_redirected(policy, n):
     """Duplicate destination rows, rows past the end (into P, H, X) and before it, and a
@@ -140,7 +150,7 @@ def test_scatter_add_redirected(policy, n):
     tw.close()
 
 
-@pytest.mark.parametrize("policy", [G.SINK, G.REPORT])
+@pytest.mark.parametrize("policy", [G.SINK, G.REPORT, G.REMAP])
 def test_copy_and_triad_redirected(policy):
     w, D = 4, 1
     ar, tw, off, dt, rng = setup(w, D, 70 + policy)
