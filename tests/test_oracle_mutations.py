@@ -13,10 +13,12 @@ import copy
 import numpy as np
 import pytest
 
+import oracle.aperture as AP
 import oracle.guarded as G
 import oracle.tokens as TK
 from oracle.table import (RangeTable, ALLOW, V_PROTECTED, V_STRADDLE, V_UNMAPPED, V_INEXACT,
                           USER, PROTECTED)
+import test_oracle_aperture as PA
 import test_oracle_guarded as PG
 import test_oracle_table as PT
 import test_oracle_tokens as PK
@@ -127,6 +129,47 @@ def test_classification_mistake_is_caught(name, monkeypatch):
     attr, fn = TABLE_MUTANTS[name]
     monkeypatch.setattr(RangeTable, attr, fn)
     assert _fails(TABLE_CHECKS), name
+
+
+# ---- planted mistakes in the aperture classification -------------------------------------
+APERTURE_CHECKS = ([PA.test_table1_apertures_fixture] +
+                   [lambda s=s: PA.test_brute_force_on_the_apertures_as_ranges(s)
+                    for s in range(10)])
+
+
+def _aperture_with(end_inclusive=False, no_straddle=False, module_is_user=False,
+                   swap_protected=False):
+    def aperture_verdict(bounds, addr, length):
+        b0, b1, b2, b3 = AP.check_bounds(bounds)
+        addr, length = int(addr), int(length)
+        if addr < b0 or addr > b3 or (addr == b3 and not end_inclusive):
+            return V_UNMAPPED, -1
+        if addr < b1:
+            return V_PROTECTED, AP.MODULE if swap_protected else AP.IO
+        if addr < b2 and not module_is_user:
+            return V_PROTECTED, AP.IO if swap_protected else AP.MODULE
+        if no_straddle or max(length, 1) <= b3 - addr:
+            return ALLOW, AP.USER_AP
+        return V_STRADDLE, AP.USER_AP
+    return aperture_verdict
+
+
+APERTURE_MUTANTS = {
+    "user aperture end counted as inside": _aperture_with(end_inclusive=True),
+    "a span past the user aperture allowed": _aperture_with(no_straddle=True),
+    "module aperture treated as user memory": _aperture_with(module_is_user=True),
+    "I/O and module indices swapped": _aperture_with(swap_protected=True),
+}
+
+
+def test_unmodified_aperture_oracle_passes_its_pins():
+    assert not _fails(APERTURE_CHECKS)
+
+
+@pytest.mark.parametrize("name", sorted(APERTURE_MUTANTS))
+def test_aperture_mistake_is_caught(name, monkeypatch):
+    monkeypatch.setattr(AP, "aperture_verdict", APERTURE_MUTANTS[name])
+    assert _fails(APERTURE_CHECKS), name
 
 
 # ---- planted mistakes in the guarded kernels --------------------------------------------
