@@ -67,7 +67,7 @@ def main():
         from paper_2606_06697_amd import _build
         _build.build()
     g.lib()
-    from synth import make_table, make_queries, uniform_f32, uniform_indices
+    from synth import make_table, make_queries, aperture_table, uniform_f32, uniform_indices
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -187,6 +187,17 @@ def main():
     dt.fault_log(clear=True)
     g.agile_rt_set_quarantine(dt.handle, 0, 0)
     torch.cuda.synchronize()
+    # the coarse aperture check (Table I's sizes, no memory attached) on queries with the same
+    # mix drawn relative to the three apertures, against the table validation above
+    ap = g.agile_aperture_create(0, (64 << 30, 448 << 30, 1 << 40))
+    ap_bounds, _, _ = g.agile_aperture_info(ap)
+    qa = make_queries(aperture_table(ap_bounds), nq, SEED, device=dev)
+    apt = time_blocks({"validate_aperture": lambda: g.agile_validate_aperture(ap, qa, nq, verdict,
+                                                                              owner)},
+                      args.warmup, args.steps)
+    torch.cuda.synchronize()
+    g.agile_aperture_destroy(ap)
+    del qa
 
     def med(x):
         return float(np.median(np.array(x)))
@@ -240,6 +251,16 @@ def main():
         "guarded_over_unguarded": {k: round(gbs_twin[k] / ugbs[k], 4) for k in ugbs},
         "overhead_pct": {k: round(100.0 * (ugbs[k] / gbs_twin[k] - 1.0), 2) for k in ugbs},
         "unguarded_frac_of_peak": {k: round(v / PEAK_HBM_GBS, 4) for k, v in ugbs.items()},
+        "aperture_check": {
+            "workload": f"{nq} queries, same mix, against Table I's three apertures "
+                        "(64 GiB I/O, 448 GiB module, 1 TiB user)",
+            "kernel_ms": round(med(apt["validate_aperture"]), 4),
+            "validations_per_s": round(nq / (med(apt["validate_aperture"]) / 1e3), 1),
+            "gbps": round(bytes_validate / med(apt["validate_aperture"]) / 1e6, 1),
+            "frac_of_peak": round(bytes_validate / med(apt["validate_aperture"]) / 1e6
+                                  / PEAK_HBM_GBS, 4),
+            "table_validate_ms": round(t_v, 4),
+            "table_over_aperture_time": round(t_v / med(apt["validate_aperture"]), 3)},
         "faults_per_step": n_bad,
         "twin_results_equal": {"triad": ok_triad, "gather": ok_gather},
         "latency_p50_ms": None,

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 LIB_NAME = "libagile_guard.so"
 LIB_PATH = os.path.join(HERE, LIB_NAME)
 SOURCES = ["runtime.hip", "k_validate.hip", "k_stream.hip", "k_gather.hip", "k_scatter_add.hip",
-           "k_batch.hip", "tokens.hip", "server.hip", "k_redirect.hip"]
+           "k_batch.hip", "tokens.hip", "server.hip", "k_redirect.hip", "aperture.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -16,6 +16,7 @@
 
 #include "device_guard.h"
 #include "agile_guard.h"
+#include "agile_aperture.h"
 #include "launch.h"
 
 using namespace agile;
@@ -359,6 +360,7 @@ const char* agile_strerror(int code) {
         case AGILE_EDEVICE: return "HIP runtime error";
         case AGILE_EFAULTED: return "guarded access denied (fault log not empty)";
         case AGILE_ETRAPPED: return "handle retired by a violation under the trap policy";
+        case AGILE_ENOTSUP: return "the device does not support virtual memory management";
         default: return "unknown status";
     }
 }

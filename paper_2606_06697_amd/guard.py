@@ -1,7 +1,7 @@
 """Python binding of libagile_guard.so (argument marshalling only).
 
 Every function here has the name of the C entry point it forwards to (see
-``include/agile_guard.h``); pointers may be given as torch tensors (their ``data_ptr()``) or
+``include/agile_guard.h`` and ``include/agile_aperture.h``); pointers may be given as torch tensors (their ``data_ptr()``) or
 as raw integer addresses, streams as ``torch.cuda.Stream``, raw handles or ``None`` (the
 current torch stream). Nothing is computed in Python: all guard work runs in the library's
 HIP kernels, and if the library is missing every call raises.
@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libagile_guard.so")
 
 AGILE_OK, AGILE_EINVAL, AGILE_ENOMEM, AGILE_EOVERLAP = 0, -1, -2, -3
 AGILE_ENOENT, AGILE_ENOSPC, AGILE_EDEVICE, AGILE_EFAULTED = -4, -5, -6, -7
-AGILE_ETRAPPED = -8
+AGILE_ETRAPPED, AGILE_ENOTSUP = -8, -9
+AP_IO, AP_MODULE, AP_USER = 0, 1, 2
 KIND_USER, KIND_PROTECTED, KIND_MMIO = 0, 1, 2
 ALLOW, V_PROTECTED, V_STRADDLE, V_UNMAPPED, V_CROSS_ALLOC, V_INEXACT = 0, 1, 2, 3, 4, 5
 (POLICY_SUPPRESS_LOG, POLICY_SUPPRESS_ONLY, POLICY_TRAP, POLICY_SINK, POLICY_REPORT,
@@ -98,6 +99,13 @@ _SIGS = {
                                    ctypes.POINTER(agile_server_config), _vp, _u64, _vp, _vp,
                                    _int]),
     "agile_server_destroy": (_int, [_vp]),
+    "agile_aperture_create": (_int, [ctypes.POINTER(_vp), _int, _vp, _vp, _u64]),
+    "agile_aperture_destroy": (_int, [_vp]),
+    "agile_aperture_info": (_int, [_vp, _vp, _vp, ctypes.POINTER(_u64)]),
+    "agile_aperture_alloc": (_int, [_vp, _int, _u64, _vp, ctypes.POINTER(_vp),
+                                    ctypes.POINTER(_i32)]),
+    "agile_aperture_free": (_int, [_vp, _vp]),
+    "agile_validate_aperture": (_int, [_vp, _vp, _u64, _vp, _vp, _vp]),
     "agile_server_run": (_int, [_vp, _vp, _vp, _vp, _u64, _vp, _vp, _u32, _vp, _vp, _vp, _vp,
                                 _vp, _vp, ctypes.POINTER(agile_server_stats)]),
 }
@@ -459,3 +467,47 @@ class RangeTable:
 
     def fault_log(self, clear: bool = False, stream=None):
         return agile_fault_log_read(self.handle, clear, stream)
+
+
+# ---- fixed address apertures (include/agile_aperture.h) -----------------------------------
+def agile_aperture_create(device: int, sizes, backed=None, base_hint: int = 0) -> int:
+    """sizes / backed: three byte counts (I/O, module, user)."""
+    sz = (ctypes.c_uint64 * 3)(*[int(x) for x in sizes])
+    bk = (ctypes.c_uint64 * 3)(*[int(x) for x in backed]) if backed is not None else None
+    h = _vp()
+    _check(lib().agile_aperture_create(ctypes.byref(h), device, ctypes.cast(sz, _vp),
+                                       ctypes.cast(bk, _vp) if bk is not None else None,
+                                       base_hint), "agile_aperture_create")
+    return h.value
+
+
+def agile_aperture_destroy(ap: int) -> None:
+    _check(lib().agile_aperture_destroy(ap), "agile_aperture_destroy")
+
+
+def agile_aperture_info(ap: int):
+    """Returns ((io start, module start, user start, user end), backed bytes per aperture,
+    granularity)."""
+    b = (ctypes.c_uint64 * 4)()
+    k = (ctypes.c_uint64 * 3)()
+    g = _u64()
+    _check(lib().agile_aperture_info(ap, ctypes.cast(b, _vp), ctypes.cast(k, _vp),
+                                     ctypes.byref(g)), "agile_aperture_info")
+    return tuple(int(x) for x in b), tuple(int(x) for x in k), g.value
+
+
+def agile_aperture_alloc(ap: int, region: int, nbytes: int, rt: int = 0):
+    """Returns (address, range id or -1)."""
+    p, rid = _vp(), _i32()
+    _check(lib().agile_aperture_alloc(ap, region, nbytes, rt or None, ctypes.byref(p),
+                                      ctypes.byref(rid)), "agile_aperture_alloc")
+    return p.value, rid.value
+
+
+def agile_aperture_free(ap: int, ptr: int) -> None:
+    _check(lib().agile_aperture_free(ap, _ptr(ptr)), "agile_aperture_free")
+
+
+def agile_validate_aperture(ap: int, q, n: int, verdict, region, stream=None) -> None:
+    _check(lib().agile_validate_aperture(ap, _ptr(q), n, _ptr(verdict), _ptr(region),
+                                         _stream(stream)), "agile_validate_aperture")

@@ -6,6 +6,6 @@ both the CPU oracle and the HIP library only ever receive what it produces.
 """
 from .workloads import (  # noqa: F401
     PAGE, KIND_USER, KIND_PROTECTED, KIND_MMIO,
-    Table, make_table, make_queries, uniform_f32, loguniform_int,
+    Table, make_table, make_queries, aperture_table, uniform_f32, loguniform_int,
     uniform_indices, zipf_indices, make_batch_requests, make_serving_trace,
 )

@@ -181,6 +181,16 @@ def make_queries(table: Table, n: int, seed: int, device="cpu",
     return out
 
 
+def aperture_table(bounds) -> Table:
+    """The three apertures ``[b0, b1)``, ``[b1, b2)``, ``[b2, b3)`` as a ``Table`` (I/O as MMIO,
+    module as PROTECTED, user as USER), so that ``make_queries`` draws its mix relative to
+    them."""
+    b = [int(x) for x in bounds]
+    return Table(torch.tensor(b[:3], dtype=torch.int64),
+                 torch.tensor([b[1] - b[0], b[2] - b[1], b[3] - b[2]], dtype=torch.int64),
+                 torch.tensor([KIND_MMIO, KIND_PROTECTED, KIND_USER], dtype=torch.uint8))
+
+
 def make_dma_queries(table: Table, n: int, seed: int, device="cpu") -> torch.Tensor:
     """``n`` DMA registration queries [n, 2] = (addr, len): 40% the exact extent of a USER
     range, 10% one byte short of it (from its base, or from base + 1), 5% one byte too long,

@@ -77,3 +77,18 @@ def test_argument_errors_fail_closed(L):
     assert L.agile_unguarded_gather(0, 0, 0, 0, 1, 0, 0) == g.AGILE_EINVAL
     assert L.agile_unguarded_gather(0, 0, 6, 0, 1, 0, 0) == g.AGILE_EINVAL
     assert L.agile_unguarded_scatter(0, 4, 0, 0, 1, 0, 2, 0) == g.AGILE_EINVAL
+    # apertures: null handles and empty apertures are rejected before any HIP call
+    assert "virtual memory" in g.strerror(g.AGILE_ENOTSUP)
+    ok3 = (ctypes.c_uint64 * 3)(1, 1, 1)
+    assert L.agile_aperture_create(None, 0, ok3, None, 0) == g.AGILE_EINVAL
+    assert L.agile_aperture_create(ctypes.byref(h), 0, None, None, 0) == g.AGILE_EINVAL
+    for bad in ((0, 1, 1), (1, 1, (1 << 48) + 1)):
+        assert L.agile_aperture_create(ctypes.byref(h), 0, (ctypes.c_uint64 * 3)(*bad), None,
+                                       0) == g.AGILE_EINVAL
+    assert L.agile_aperture_create(ctypes.byref(h), 0, ok3, (ctypes.c_uint64 * 3)(1, 2, 1),
+                                   0) == g.AGILE_EINVAL     # backing larger than its aperture
+    assert L.agile_aperture_info(None, None, None, None) == g.AGILE_EINVAL
+    assert L.agile_aperture_alloc(None, 2, 16, None, None, None) == g.AGILE_EINVAL
+    assert L.agile_aperture_free(None, None) == g.AGILE_EINVAL
+    assert L.agile_validate_aperture(None, 0, 1, 0, 0, 0) == g.AGILE_EINVAL
+    assert L.agile_aperture_destroy(None) == g.AGILE_OK
