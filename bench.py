@@ -113,7 +113,10 @@ def main():
     step_bytes = bytes_validate + bytes_triad + bytes_gather
 
     if args.counters_pass:
+        ap = g.agile_aperture_create(0, (64 << 30, 448 << 30, 1 << 40))
+        qa = make_queries(aperture_table(g.agile_aperture_info(ap)[0]), nq, SEED, device=dev)
         for _ in range(3):
+            g.agile_validate_aperture(ap, qa, nq, verdict, owner)
             g.agile_validate_ptrs(vt.handle, q, nq, verdict, owner)
             g.agile_guarded_triad(dt.handle, a, b, c, 3.0, TRIAD_N)
             g.agile_unguarded_triad(a_ref, b, c, 3.0, TRIAD_N)
@@ -122,8 +125,10 @@ def main():
             g.agile_unguarded_copy(a_ref, b, 4 * TRIAD_N)      # reference: 1 GiB in, 1 GiB out
         dt.fault_log(clear=True)
         torch.cuda.synchronize()
+        g.agile_aperture_destroy(ap)
         print(json.dumps({"counters_pass": True, "bytes_per_launch": {
-            "validate": nq * 21, "triad": TRIAD_N * 12, "gather": GATHER_N * 16,
+            "validate": nq * 21, "validate_aperture": nq * 21, "triad": TRIAD_N * 12,
+            "gather": GATHER_N * 16,
             "copy_reference": {"read": 4 * TRIAD_N, "write": 4 * TRIAD_N}}}), flush=True)
         return
 
