@@ -188,6 +188,8 @@ def main():
                                                       g.POLICY_SINK),
         "gather_report": lambda: g.agile_guarded_gather(dt.handle, out, table, 4, idx, GATHER_N,
                                                         0, g.POLICY_REPORT),
+        "gather_remap": lambda: g.agile_guarded_gather(dt.handle, out, table, 4, idx, GATHER_N,
+                                                       0, g.POLICY_REMAP),
     }, args.warmup, args.steps)
     dt.fault_log(clear=True)
     g.agile_rt_set_quarantine(dt.handle, 0, 0)
@@ -249,6 +251,7 @@ def main():
                       "gather": round(t_g, 4), "triad_unguarded": round(ug_t, 4),
                       "gather_sink": round(med(pol["gather_sink"]), 4),
                       "gather_report": round(med(pol["gather_report"]), 4),
+                      "gather_remap": round(med(pol["gather_remap"]), 4),
                       "gather_unguarded": round(ug_g, 4)},
         "guarded_gbps": {k: round(v, 1) for k, v in gbs.items()},
         "unguarded_gbps": {k: round(v, 1) for k, v in ugbs.items()},

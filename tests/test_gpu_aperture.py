@@ -261,3 +261,40 @@ def test_allocations_are_registered_and_guarded():
         g.agile_aperture_destroy(ap)
     assert len(tw.rt) == 0       # destroy removed what was still registered
     tw.close()
+
+
+def test_full_size_sampled():
+    """2^28 queries with the bench's mix against Table I's sizes (placed by the runtime), in
+    the launch the bench times; 2^20 sampled outputs against the oracle, and the verdict
+    histogram of the whole output against the oracle's on the same inputs drawn again on the
+    host in chunks."""
+    need_gpu()
+    g = guard_mod()
+    from synth import aperture_table, make_queries
+    n = 1 << 28
+    ap = g.agile_aperture_create(0, (64 << 30, 448 << 30, 1 << 40))
+    try:
+        bounds, _, _ = g.agile_aperture_info(ap)
+        q = make_queries(aperture_table(bounds), n, 11, device="cuda")
+        v = torch.empty(n, dtype=torch.uint8, device="cuda")
+        r = torch.empty(n, dtype=torch.int32, device="cuda")
+        g.agile_validate_aperture(ap, q, n, v, r)
+        torch.cuda.synchronize()
+        rng = np.random.default_rng(11)
+        pos = np.sort(rng.choice(n, 1 << 20, replace=False))
+        pos_t = torch.from_numpy(pos).cuda()
+        qs = q[pos_t].cpu().numpy().view(np.uint64)
+        ev, er = AP.aperture_verdict_many(bounds, qs[:, 0], qs[:, 1])
+        assert np.array_equal(v[pos_t].cpu().numpy(), ev)
+        assert np.array_equal(r[pos_t].cpu().numpy(), er)
+        # the whole output: per-verdict counts equal the oracle's on every query
+        counts = torch.bincount(v.long(), minlength=4).cpu().numpy()
+        want = np.zeros(4, dtype=np.int64)
+        for c0 in range(0, n, 1 << 24):
+            qc = q[c0:c0 + (1 << 24)].cpu().numpy().view(np.uint64)
+            want += np.bincount(AP.aperture_verdict_many(bounds, qc[:, 0], qc[:, 1])[0],
+                                minlength=4)
+        assert np.array_equal(counts[:4], want)
+        del q, v, r
+    finally:
+        g.agile_aperture_destroy(ap)
