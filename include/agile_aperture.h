@@ -74,9 +74,9 @@ int agile_aperture_info(const agile_aperture* ap, uint64_t* bounds, uint64_t* ba
 int agile_aperture_alloc(agile_aperture* ap, int region, uint64_t bytes, agile_rt* rt,
                          void** out_ptr, int32_t* out_id);
 
-/* Release an allocation made by agile_aperture_alloc (`ptr` exactly as returned): its range
- * is removed from the table it was registered in, all work on the device is waited for, and
- * its addresses become free again in the aperture (the backing stays mapped).
+/* Release an allocation made by agile_aperture_alloc (`ptr` exactly as returned): all work on
+ * the device is waited for, its range is removed from the table it was registered in, and its
+ * addresses become free again in the aperture (the backing stays mapped).
  * Errors: EINVAL, ENOENT (not a live allocation of this aperture), EDEVICE. */
 int agile_aperture_free(agile_aperture* ap, void* ptr);
 

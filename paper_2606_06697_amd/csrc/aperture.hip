@@ -304,9 +304,9 @@ int agile_aperture_free(agile_aperture* ap, void* ptr) {
     auto it = ap->allocs.find(reinterpret_cast<uint64_t>(ptr));
     if (it == ap->allocs.end()) return AGILE_ENOENT;
     DeviceGuard dg(ap->device);
-    if (!dg.ok) return AGILE_EDEVICE;
+    // wait first: on a failure nothing has changed
+    if (!dg.ok || hipDeviceSynchronize() != hipSuccess) return AGILE_EDEVICE;
     if (it->second.rt) (void)agile_rt_remove(it->second.rt, it->second.id);
-    if (hipDeviceSynchronize() != hipSuccess) return AGILE_EDEVICE;
     ap->va[it->second.region].give(it->first, it->second.bytes);
     ap->allocs.erase(it);
     return AGILE_OK;
