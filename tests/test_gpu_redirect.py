@@ -192,3 +192,32 @@ def test_sink_without_quarantine_is_refused():
         with pytest.raises(g.AgileError):
             g.agile_rt_set_quarantine(tw.h, *bad)
     tw.close()
+
+
+def test_remap_rounds_an_unaligned_binding_up():
+    """REMAP with a USER range that starts at an odd address and has an odd size: rewritten
+    accesses go to lo' = lo rounded up to 4 plus a multiple of 4 below m = the largest multiple
+    of 4 not above hi - lo'. Denied loads (b runs past the range) and denied stores (a runs
+    past it) against the oracle; the rewritten stores land below the allowed ones."""
+    need_gpu()
+    ar = Arena(1 << 16, 91)
+    tw = Twin(8)
+    g = tw.g
+    U0, U1 = 1, 1 + 4001
+    tw.insert(ar.addr(U0), U1 - U0, 0)
+    tw.insert(ar.addr(8192), 4096, 0)     # C
+    tw.insert(ar.addr(16384), 4096, 0)    # X
+    rng = np.random.default_rng(91)
+    for off, size in ((0, 1 << 14), (16384, 4096)):
+        ar.write(off, rng.integers(-20, 21, size // 4).astype(np.float32))
+    ol = G.FaultLog()
+    C, X = ar.addr(8192), ar.addr(16384)
+    b = ar.addr(4)                          # inside U, 4-aligned; elements 999.. are denied
+    run_both(tw, ar, lambda: g.agile_guarded_triad(tw.h, C, b, X, 2.0, 1024, G.REMAP),
+             lambda: G.triad_loop(tw.ot, ar.mem, ol, tw.next_seq(), C, b, X, 2.0, 1024, G.REMAP),
+             ol, "remap, unaligned binding, denied loads")
+    a = ar.addr(2000)                       # elements 500.. are denied stores
+    run_both(tw, ar, lambda: g.agile_guarded_triad(tw.h, a, C, X, 2.0, 600, G.REMAP),
+             lambda: G.triad_loop(tw.ot, ar.mem, ol, tw.next_seq(), a, C, X, 2.0, 600, G.REMAP),
+             ol, "remap, unaligned binding, denied stores")
+    tw.close()
