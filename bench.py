@@ -48,6 +48,9 @@ def parse():
     p.add_argument("--counters-pass", action="store_true",
                    help="only launch each large-table kernel a few times, plus a plain 1 GiB copy "
                         "(the reference for scaling HBM counters), for a rocprofv3 --pmc run")
+    p.add_argument("--extra", choices=("small_guard", "tokens", "embedding", "batch"),
+                   help="run only this workload, then a plain 1 GiB copy (the reference for "
+                        "scaling HBM counters), and print its JSON object")
     p.add_argument("--queries-log2", type=int, default=28, help=argparse.SUPPRESS)
     return p.parse_args()
 
@@ -71,6 +74,19 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.extra:
+        fn = {"small_guard": bench_small_guard, "tokens": bench_tokens,
+              "embedding": lambda g_: bench_embedding(g_, args),
+              "batch": lambda g_: bench_batch(g_, args)}[args.extra]
+        out = fn(g)
+        torch.cuda.empty_cache()
+        ref_a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        ref_b = torch.zeros(1 << 30, dtype=torch.uint8, device=dev)
+        for _ in range(3):
+            g.agile_unguarded_copy(ref_a, ref_b, 1 << 30)   # reference: 1 GiB in, 1 GiB out
+        torch.cuda.synchronize()
+        print(json.dumps({"extra": args.extra, **out}), flush=True)
+        return
     nq = 1 << args.queries_log2
 
     # ---------------- inputs (resident before timing) ----------------
