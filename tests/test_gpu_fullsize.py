@@ -276,3 +276,78 @@ def test_batched_launch_16_clients_512_requests():
         rt.close()
     del src, dst, P, pv, po, res
     _free()
+
+
+def test_redirecting_policies_full_size_gather():
+    """The bench's gather (2^26 indices over 2^28 rows, 0.1% aimed at a protected pad or an
+    unregistered hole) under SINK (64 KiB quarantine), REPORT and REMAP. Every hostile row is
+    checked: its target comes from the oracle's per-access rule and its value from the buffer
+    that holds the target (zero when the access stays suppressed). Sampled allowed rows are the
+    table element; the count and first record equal the suppress-and-log ones."""
+    need_gpu()
+    g = guard_mod()
+    ROWS, NI, PAD, QS = 1 << 28, 1 << 26, 64 << 10, 1 << 16
+    dt = g.RangeTable(16)
+    ot = OracleTable()
+    gbuf = torch.empty(ROWS * 4 + 2 * PAD, dtype=torch.uint8, device="cuda")
+    table = gbuf[:ROWS * 4].view(torch.float32)
+    table.copy_(uniform_f32(ROWS, 2, device="cuda", stream=12))
+    gbuf[ROWS * 4:].fill_(0xA5)
+    idx = uniform_indices(NI, ROWS, 2, device="cuda", bad_frac=0.001,
+                          bad_ranges=((ROWS, ROWS + PAD // 4), (ROWS + PAD // 4, ROWS + PAD // 2)))
+    out = torch.empty(NI, dtype=torch.float32, device="cuda")
+    quar = uniform_f32(QS // 4, 3, device="cuda", stream=13)
+    qh = quar.cpu().numpy()
+    T = table.data_ptr()
+    for ptr, size, kind in ((idx.data_ptr(), NI * 8, 0), (out.data_ptr(), NI * 4, 0),
+                            (T, ROWS * 4, 0), (T + ROWS * 4, PAD, 1)):
+        assert dt.insert(ptr, size, kind) == ot.insert(ptr, size, kind)
+    g.agile_rt_set_quarantine(dt.handle, quar, QS)
+    bad = (idx < 0) | (idx >= ROWS)
+    ib = torch.nonzero(bad).flatten()
+    bad_rows = idx[ib].cpu().numpy()
+    nbad = bad_rows.size
+    pos = _sample_positions(NI, 14).cuda()
+    ip = idx[pos].cpu().numpy()
+    okp = (ip >= 0) & (ip < ROWS)
+    tv = table[torch.from_numpy(ip[okp]).cuda()].cpu().numpy()
+    bind = ot.binding(T)
+    first = None
+    for seq, policy in enumerate((G.SUPPRESS_LOG, G.SINK, G.REPORT, G.REMAP)):
+        out.fill_(7.0)
+        g.agile_guarded_gather(dt.handle, out, table, 4, idx, NI, 0, policy)
+        rc, f = dt.fault_log(clear=True)
+        assert rc == g.AGILE_EFAULTED and f["count"] == nbad, policy
+        rec = (f["first_elem"], f["first_operand"], f["first_addr"], f["first_verdict"],
+               f["first_owner"])
+        assert f["first_seq"] == seq
+        first = first or rec
+        assert rec == first, policy
+        # every hostile row: the oracle's target, read from the buffer that holds it
+        den = G._Denier(ot, G.FaultLog(), seq, G.OP_GATHER, policy, quarantine=(quar.data_ptr(), QS))
+        want = np.zeros(nbad, dtype=np.uint32)
+        tgt_rows = []
+        for k, r in enumerate(bad_rows.tolist()):
+            t = den.target(T + 4 * r, 4, bind)
+            if t is None:
+                continue
+            if T <= t < T + ROWS * 4:
+                tgt_rows.append((k, (t - T) // 4))
+            elif T + ROWS * 4 <= t < T + ROWS * 4 + PAD:
+                want[k] = 0xA5A5A5A5
+            else:
+                assert quar.data_ptr() <= t < quar.data_ptr() + QS
+                want[k] = qh[(t - quar.data_ptr()) // 4].view(np.uint32)
+        if tgt_rows:
+            ks, rows_ = zip(*tgt_rows)
+            vals = table[torch.tensor(rows_, device="cuda")].cpu().numpy().view(np.uint32)
+            want[list(ks)] = vals
+        got = out[ib].cpu().numpy().view(np.uint32)
+        assert np.array_equal(got, want), (policy, int((got != want).sum()))
+        op = out[pos].cpu().numpy()
+        assert np.array_equal(op[okp].view(np.uint32), tv.view(np.uint32)), policy
+        assert bool((gbuf[ROWS * 4:] == 0xA5).all())
+    g.agile_rt_set_quarantine(dt.handle, 0, 0)
+    dt.close()
+    del gbuf, table, idx, out, quar
+    _free()
