@@ -205,7 +205,8 @@ int agile_aperture_create(agile_aperture** out, int device, const uint64_t* size
     // back to back at that address.
     bool placed = base_hint && base_hint <= ~0ull - 1 - total && reserve_at(ap, base_hint, sz);
     ap->user_hint = placed;
-    if (!placed) {
+    // (another thread may take the released range first: a few attempts)
+    for (int attempt = 0; attempt < 4 && !placed; ++attempt) {
         void* p = nullptr;
         if (hipMemAddressReserve(&p, total, g, nullptr, 0) == hipSuccess && p) {
             const uint64_t b0 = reinterpret_cast<uint64_t>(p);
