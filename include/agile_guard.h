@@ -7,8 +7,10 @@
  * and live size), batched API-time pointer validation and the DMA registration check
  * (Section IV-E, V-C), and guarded kernels whose every global access is checked before it
  * happens, with the paper's poison (record, fail later), sink (to a zero page or a
- * quarantine), report and trap (retire) policies (Section V-E). Around them: client handle tokens (Section IV-C), a batched
+ * quarantine), report, remap_or (restricted to the argument's own allocation) and trap
+ * (retire) policies (Section V-E). Around them: client handle tokens (Section IV-C), a batched
  * multi-client launch and a native serving loop with revocation (Sections IV-B, IV-D).
+ * agile_aperture.h adds Table I's fixed apertures and their coarse check (Sections IV-E, V-A).
  *
  * Conventions for every entry point
  *  - Return value: AGILE_OK (0) or a negative AGILE_E* code; nothing is thrown across the
