@@ -399,6 +399,10 @@ typedef struct {
     uint64_t launches;
     uint64_t served;
     uint64_t refused;       /* revoked client, or an output larger than its ring or the budget */
+    uint64_t max_inflight_bytes;  /* most output bytes in flight at once (at most hbm_budget) */
+    uint64_t max_concurrent;      /* most launches in flight at once (at most max_inflight) */
+    uint64_t budget_waits;  /* requests that reached the FIFO head and waited for budget */
+    uint64_t ring_waits;    /* requests that reached the FIFO head and waited for ring space */
     double revoked_at_s[AGILE_SERVER_MAX_REVOKE]; /* when each revocation took effect */
 } agile_server_stats;
 

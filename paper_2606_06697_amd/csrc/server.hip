@@ -148,6 +148,15 @@ int agile_server_run(agile_server* sv, agile_request* reqs, const uint64_t* out_
     std::vector<agile_request> batch;
     batch.reserve(sv->cfg.max_batch);
     uint64_t nxt = 0, done = 0, launches = 0, refused = 0, inflight_bytes = 0;
+    uint64_t max_inflight_bytes = 0, max_concurrent = 0, budget_waits = 0, ring_waits = 0;
+    // why the FIFO head last waited (1 budget, 2 ring), so each request is counted once
+    std::vector<uint8_t> waited(n, 0);
+    auto note_wait = [&](uint64_t r, uint8_t why) {
+        if (waited[r] & why) return;
+        waited[r] |= why;
+        if (why == 1) ++budget_waits;
+        else ++ring_waits;
+    };
     const auto t0 = std::chrono::steady_clock::now();
     auto clock = [&]() {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -231,10 +240,16 @@ int agile_server_run(agile_server* sv, agile_request* reqs, const uint64_t* out_
                     ++done;
                     continue;
                 }
-                if (inflight_bytes + nbytes + need > sv->cfg.hbm_budget) break;
+                if (inflight_bytes + nbytes + need > sv->cfg.hbm_budget) {
+                    note_wait(r, 1);  // admitted once earlier launches return their bytes
+                    break;
+                }
                 if (need) {
                     uint64_t start, addr;
-                    if (!sv->rings[rq.client].alloc(need, &start, &addr)) break;
+                    if (!sv->rings[rq.client].alloc(need, &start, &addr)) {
+                        note_wait(r, 2);  // admitted once the client's ring drains
+                        break;
+                    }
                     if (rq.copy_bytes) rq.copy_dst = addr;
                     else rq.gather_out = addr;
                     sl.allocs.emplace_back(rq.client, start);
@@ -255,6 +270,10 @@ int agile_server_run(agile_server* sv, agile_request* reqs, const uint64_t* out_
                 inflight_bytes += nbytes;
                 sl.busy = true;
                 ++launches;
+                uint64_t busy = 0;
+                for (const Slot& o : sv->slots) busy += o.busy ? 1 : 0;
+                max_concurrent = std::max(max_concurrent, busy);
+                max_inflight_bytes = std::max(max_inflight_bytes, inflight_bytes);
                 continue;
             }
         }
@@ -273,6 +292,10 @@ int agile_server_run(agile_server* sv, agile_request* reqs, const uint64_t* out_
         stats->launches = launches;
         stats->refused = refused;
         stats->served = n - refused;
+        stats->max_inflight_bytes = max_inflight_bytes;
+        stats->max_concurrent = max_concurrent;
+        stats->budget_waits = budget_waits;
+        stats->ring_waits = ring_waits;
     }
     // revocation times, for the caller (NaN where a revocation was not reached)
     if (stats)

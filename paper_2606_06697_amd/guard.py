@@ -63,6 +63,8 @@ class agile_server_config(ctypes.Structure):
 class agile_server_stats(ctypes.Structure):
     _fields_ = [("elapsed_s", ctypes.c_double), ("launches", ctypes.c_uint64),
                 ("served", ctypes.c_uint64), ("refused", ctypes.c_uint64),
+                ("max_inflight_bytes", ctypes.c_uint64), ("max_concurrent", ctypes.c_uint64),
+                ("budget_waits", ctypes.c_uint64), ("ring_waits", ctypes.c_uint64),
                 ("revoked_at_s", ctypes.c_double * SERVER_MAX_REVOKE)]
 
 _SIGS = {

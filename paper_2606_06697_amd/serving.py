@@ -213,6 +213,10 @@ class Server:
             "mean_batch": float(ok.sum() / max(st.launches, 1)),
             "moved_gb_per_s": moved / st.elapsed_s / 1e9,
             "refused": int(st.refused),
+            "max_inflight_bytes": int(st.max_inflight_bytes),
+            "max_concurrent_launches": int(st.max_concurrent),
+            "budget_waits": int(st.budget_waits),
+            "ring_waits": int(st.ring_waits),
         }
         return lat, stats, kept
 

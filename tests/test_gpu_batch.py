@@ -29,9 +29,9 @@ NSLOT = (ARENA - SLOTS) // SLOT
 
 
 class Client:
-    def __init__(self, g, c):
-        self.tb = make_table(200, 40, 100 + c, first_hi=2**44)
-        self.rt = g.RangeTable(512)
+    def __init__(self, g, c, n_ranges=200):
+        self.tb = make_table(n_ranges, n_ranges // 5, 100 + c, first_hi=2**44)
+        self.rt = g.RangeTable(n_ranges + 312)
         self.ot = OracleTable()
         self.rt.insert_many(self.tb.base, self.tb.size, self.tb.kind)
         for b, s, k in zip(self.tb.base.tolist(), self.tb.size.tolist(), self.tb.kind.tolist()):
@@ -59,9 +59,9 @@ class Client:
         return self.base + off
 
 
-def build(seed, ncl=4, nreq=40):
+def build(seed, ncl=4, nreq=40, n_ranges=200):
     g = guard_mod()
-    cls = [Client(g, c) for c in range(ncl)]
+    cls = [Client(g, c, n_ranges) for c in range(ncl)]
     rng = random.Random(seed)
     reqs = np.zeros(nreq, dtype=g.REQUEST_DTYPE)
     ptrs = []
@@ -140,10 +140,16 @@ def check_fault(res, log, r, seq):
     assert got == want and int(res["first_seq"]) == seq, (r, got, want)
 
 
-@pytest.mark.parametrize("seed", [1, 2, 3])
-def test_batch_against_oracle_and_alone_identity(seed):
+@pytest.mark.parametrize("seed,n_ranges", [(1, 200), (2, 200), (3, 200), (4, 9000),
+                                            (5, 20000)])
+def test_batch_against_oracle_and_alone_identity(seed, n_ranges):
+    """Client tables of 200 ranges have their bucket splitters staged in LDS; tables of 9,000
+    and 20,000 ranges (more than 4,096 buckets) are searched in global memory."""
     need_gpu()
-    g, cls, reqs, P, nptrs = build(seed)
+    g, cls, reqs, P, nptrs = build(seed, n_ranges=n_ranges)
+    if n_ranges > 8192:
+        counts = [len(cl.rt) for cl in cls]
+        assert min(counts) > 8192, counts   # more than 4,096 buckets: the unstaged search
     cs = g.agile_clients_create([cl.rt for cl in cls])
     pv, po, res = run_batch(g, cs, reqs, P, nptrs)
     # pointer verdicts and per-request lowest failing argument

@@ -9,26 +9,9 @@ from gpu_util import need_gpu, guard_mod
 pytestmark = pytest.mark.gpu
 
 
-def test_serving_mix_equals_alone():
-    need_gpu()
-    g = guard_mod()
-    from paper_2606_06697_amd.serving import Server, ServeConfig
-    from synth import make_serving_trace
-    cfg = ServeConfig(n_clients=6, rate=20000.0, duration=0.3, ranges=(256, 1024),
-                      gather_table_bytes=16 << 20, idx_pool=1 << 16, copy_src_bytes=2 << 20,
-                      ptr_pool=1 << 13, ring_bytes=64 << 20, hbm_budget=1 << 30, max_batch=128,
-                      copy_range=(4096, 2 << 20), gather_range=(1 << 12, 1 << 16))
-    srv = Server(cfg)
-    trace = make_serving_trace(cfg.n_clients, cfg.rate, cfg.duration, cfg.seed,
-                               mix=cfg.mix, val_ptrs=cfg.val_ptrs, copy_range=cfg.copy_range,
-                               gather_range=cfg.gather_range)
-    n = trace["t"].numel()
-    rng = np.random.default_rng(0)
-    sample = set(rng.choice(n, size=min(150, n), replace=False).tolist())
-    lat, stats, kept = srv.run(trace, record=sample)
-    assert stats["requests"] == n and not np.isnan(lat).any()
-    assert stats["launches"] < n                      # requests were batched
-    assert len(kept) == len(sample)
+def check_against_alone_and_oracle(srv, kept):
+    """Every kept result equals the same request run alone; copies carry the source bytes and
+    gathers the table rows (0 for a denied index, with the denial counted)."""
     for r, (res, out, pv, po, q) in kept.items():
         assert res["done"] == 1
         ares, aout, apv, apo = srv.run_alone(q)
@@ -53,6 +36,69 @@ def test_serving_mix_equals_alone():
             want[ok] = tab[iv[ok]]
             assert np.array_equal(out.view(np.float32), want)
             assert res["count"] == int((~ok).sum())
+
+
+def test_serving_mix_equals_alone():
+    need_gpu()
+    g = guard_mod()
+    from paper_2606_06697_amd.serving import Server, ServeConfig
+    from synth import make_serving_trace
+    cfg = ServeConfig(n_clients=6, rate=20000.0, duration=0.3, ranges=(256, 1024),
+                      gather_table_bytes=16 << 20, idx_pool=1 << 16, copy_src_bytes=2 << 20,
+                      ptr_pool=1 << 13, ring_bytes=64 << 20, hbm_budget=1 << 30, max_batch=128,
+                      copy_range=(4096, 2 << 20), gather_range=(1 << 12, 1 << 16))
+    srv = Server(cfg)
+    trace = make_serving_trace(cfg.n_clients, cfg.rate, cfg.duration, cfg.seed,
+                               mix=cfg.mix, val_ptrs=cfg.val_ptrs, copy_range=cfg.copy_range,
+                               gather_range=cfg.gather_range)
+    n = trace["t"].numel()
+    rng = np.random.default_rng(0)
+    sample = set(rng.choice(n, size=min(150, n), replace=False).tolist())
+    lat, stats, kept = srv.run(trace, record=sample)
+    assert stats["requests"] == n and not np.isnan(lat).any()
+    assert stats["launches"] < n                      # requests were batched
+    assert stats["max_inflight_bytes"] <= cfg.hbm_budget
+    assert len(kept) == len(sample)
+    check_against_alone_and_oracle(srv, kept)
+    srv.close()
+
+
+def test_serving_admission_waits_for_budget_and_ring_space():
+    """A burst of 400 requests in 2 ms against an 8 MiB budget for in-flight outputs and 2 MiB
+    output rings per client: the FIFO head has to wait for both (counted per request), the
+    bytes in flight never exceed the budget, several launches are in flight together, and
+    requests are admitted as earlier launches return their output space (launched after the
+    first completion). Every sampled result still equals the request run alone and the
+    oracle."""
+    need_gpu()
+    guard_mod()
+    from paper_2606_06697_amd.serving import Server, ServeConfig
+    from synth import make_serving_trace
+    budget = 8 << 20
+    cfg = ServeConfig(n_clients=6, rate=200000.0, duration=0.002, ranges=(256, 1024),
+                      gather_table_bytes=16 << 20, idx_pool=1 << 16, copy_src_bytes=2 << 20,
+                      ptr_pool=1 << 13, ring_bytes=2 << 20, hbm_budget=budget, max_batch=4,
+                      max_inflight=4, val_ptrs=(16, 256), copy_range=(256 << 10, 1536 << 10),
+                      gather_range=(1 << 12, 1 << 16), mix=(0.2, 0.6, 0.2))
+    srv = Server(cfg)
+    trace = make_serving_trace(cfg.n_clients, cfg.rate, cfg.duration, cfg.seed,
+                               mix=cfg.mix, val_ptrs=cfg.val_ptrs, copy_range=cfg.copy_range,
+                               gather_range=cfg.gather_range)
+    n = trace["t"].numel()
+    assert n > 300
+    rng = np.random.default_rng(3)
+    sample = set(rng.choice(n, size=120, replace=False).tolist())
+    lat, stats, kept = srv.run(trace, record=sample)
+    assert stats["requests"] == n and stats["refused"] == 0 and not np.isnan(lat).any()
+    assert 0 < stats["max_inflight_bytes"] <= budget
+    assert stats["budget_waits"] > 0 and stats["ring_waits"] > 0, stats
+    assert 2 <= stats["max_concurrent_launches"] <= cfg.max_inflight, stats
+    arr = trace["t"].numpy()
+    first_done = float(np.min(arr + lat))
+    later = srv.t_launch > first_done
+    assert later.sum() > n // 4                      # admitted as output space came back
+    assert (srv.t_launch >= arr).all()
+    check_against_alone_and_oracle(srv, kept)
     srv.close()
 
 
