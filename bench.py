@@ -118,8 +118,9 @@ def main():
     dt.insert_many(tb.base, tb.size, tb.kind)
     for t in (a, b, c, idx, out):
         dt.insert_tensor(t)
-    dt.insert(table.data_ptr(), GATHER_ROWS * 4, g.KIND_USER)
-    dt.insert(table.data_ptr() + GATHER_ROWS * 4, PAD_BYTES, g.KIND_PROTECTED)
+    # the table and the protected pad after it are device memory (the synthetic ranges are not)
+    dt.insert(table.data_ptr(), GATHER_ROWS * 4, g.KIND_USER, backed=True)
+    dt.insert(table.data_ptr() + GATHER_ROWS * 4, PAD_BYTES, g.KIND_PROTECTED, backed=True)
     n_bad = int(((idx < 0) | (idx >= GATHER_ROWS)).sum())
     torch.cuda.synchronize()
 

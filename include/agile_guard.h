@@ -61,6 +61,11 @@ enum {
 /* Range kinds (Table I): user allocations, protected module/service memory, MMIO. */
 enum { AGILE_KIND_USER = 0, AGILE_KIND_PROTECTED = 1, AGILE_KIND_MMIO = 2 };
 
+/* Flag OR-ed into a kind at insertion: the caller states that every byte of the range is
+ * mapped device memory that a kernel may touch. Only the REPORT policy reads it (it performs a
+ * denied access only inside such a range); classification ignores it. */
+enum { AGILE_RANGE_BACKED = 0x80 };
+
 /* Verdicts. The owner of the first byte decides: no owner -> UNMAPPED; a protected or
  * MMIO owner -> PROTECTED; a USER owner -> ALLOW if max(len,1) <= end - addr, else
  * STRADDLE (the byte range must stay inside one live allocation, Section V-C).
@@ -101,7 +106,8 @@ enum {
  * multiple of w: denied loads read it, denied stores write it, denied scatter-adds add into it
  * (atomically). REPORT (Section V-E "report": log would-be violations without enforcing): a
  * denied access is performed at A when [A, A+w) lies inside one registered range of the table
- * (any kind); outside every range it stays suppressed, since such memory may not be mapped.
+ * (any kind) that was inserted with AGILE_RANGE_BACKED; everywhere else (outside every range,
+ * or in a range not declared backed, which may have no memory behind it) it stays suppressed.
  * Both log every denial as SUPPRESS_LOG does, and both run a second pass after the guarded
  * kernel on the same stream. Denied accesses of one call that reach the same quarantine slot
  * or address are unordered (like duplicate indices of a plain scatter). SINK without a
@@ -168,7 +174,8 @@ int agile_rt_create(agile_rt** out, uint32_t capacity, int device);
  * IV-D, lifetime and revocation). NULL is accepted. */
 int agile_rt_destroy(agile_rt* rt);
 
-/* Insert the half-open range [base, base+size) of `kind`. Requires size >= 1 and
+/* Insert the half-open range [base, base+size) of `kind` (an AGILE_KIND_*, optionally OR-ed
+ * with AGILE_RANGE_BACKED; any other bit is EINVAL). Requires size >= 1 and
  * base + size <= 2^64 - 1. Adjacent ranges are legal; any intersection gives EOVERLAP.
  * *out_id (may be NULL) receives the new stable id: 0, 1, 2, ... in insertion order,
  * never reused. Errors: EINVAL, EOVERLAP, ENOSPC. */
@@ -176,7 +183,8 @@ int agile_rt_insert(agile_rt* rt, uint64_t base, uint64_t size, uint32_t kind,
                     int32_t* out_id);
 
 /* Insert n ranges (host arrays) as one all-or-nothing batch, in array order; ids are
- * assigned in that order. out_ids (may be NULL) receives n ids. */
+ * assigned in that order. kind[i] as for agile_rt_insert. out_ids (may be NULL) receives n
+ * ids. */
 int agile_rt_insert_many(agile_rt* rt, const uint64_t* base, const uint64_t* size,
                          const uint8_t* kind, uint32_t n, int32_t* out_ids);
 

@@ -28,8 +28,9 @@ access is redirected to a caller-provided quarantine of ``qsize`` bytes (a power
 ``qbase``: the access of width ``w`` at ``A`` goes to ``qbase + ((A mod 2**64) mod qsize)``
 rounded down to a multiple of ``w`` (loads read it, stores write it, scatter-add adds into
 it). Under ``REPORT`` a denied access is performed at ``A`` itself when ``[A, A+w)`` lies inside
-one registered range of any kind (memory the table vouches for), and suppressed otherwise
-(memory outside every range may not be mapped). Under ``REMAP`` (the paper's ``remap_or``,
+one registered range of any kind that was inserted as backed (the caller vouches that it is
+mapped memory), and suppressed otherwise (memory outside every range, or in a range with no
+such statement, may not be mapped). Under ``REMAP`` (the paper's ``remap_or``,
 kept to the condition under which the paper calls it safe: the target is a live user
 allocation) a denied access is rewritten into its own argument's allocation ``[lo, hi)``:
 with ``lo'`` = lo rounded up to a multiple of ``w`` and ``m`` the largest multiple of ``w``
@@ -142,7 +143,7 @@ class _Denier:
             if A < 0 or A + w > (1 << 64):
                 return None
             ent = self.t.owner_entry(A)
-            if ent is not None and A + w <= ent[1]:
+            if ent is not None and A + w <= ent[1] and self.t.is_backed(ent[3]):
                 return A
         return None
 

@@ -43,12 +43,15 @@ class RangeTable:
         self._bases: list[int] = []          # sorted
         self._by_base: dict[int, tuple] = {}  # base -> (end, kind, id)
         self._by_id: dict[int, int] = {}      # id -> base
+        self._backed: set[int] = set()        # ids of ranges declared backed (mapped memory)
         self._next_id = 0
 
     def __len__(self):
         return len(self._bases)
 
-    def insert(self, base: int, size: int, kind: int) -> int:
+    def insert(self, base: int, size: int, kind: int, backed: bool = False) -> int:
+        """Add [base, base+size) of ``kind``; ``backed`` records the caller's statement that the
+        range is mapped memory (read only by the ``report`` policy)."""
         base, size, kind = int(base), int(size), int(kind)
         if kind not in (USER, PROTECTED, MMIO):
             raise ValueError("unknown kind")
@@ -67,12 +70,18 @@ class RangeTable:
         self._bases.insert(k, base)
         self._by_base[base] = (end, kind, rid)
         self._by_id[rid] = base
+        if backed:
+            self._backed.add(rid)
         return rid
+
+    def is_backed(self, rid: int) -> bool:
+        return int(rid) in self._backed
 
     def remove(self, rid: int) -> None:
         """Free a range: its bytes become a hole (freed allocations are rejected)."""
         base = self._by_id.pop(int(rid))  # KeyError for unknown or already-removed ids
         del self._by_base[base]
+        self._backed.discard(int(rid))
         self._bases.pop(bisect.bisect_left(self._bases, base))
 
     def entries(self):

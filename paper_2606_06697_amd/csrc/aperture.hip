@@ -290,7 +290,8 @@ int agile_aperture_alloc(agile_aperture* ap, int region, uint64_t bytes, agile_r
     if (!ap->va[region].take(n, &addr)) return AGILE_ENOSPC;
     int32_t id = -1;
     if (rt) {
-        const int rc = agile_rt_insert(rt, addr, bytes, kind_of(region), &id);
+        // carved from the aperture's mapped backing: memory a kernel may touch
+        const int rc = agile_rt_insert(rt, addr, bytes, kind_of(region) | AGILE_RANGE_BACKED, &id);
         if (rc != AGILE_OK) {
             ap->va[region].give(addr, n);
             return rc;

@@ -10,6 +10,7 @@
 //                    (addr - gmin) >> shift then orders exactly like the address
 //   rec[b]      32 B {base of the 2nd range (U64 max if none), end of 1st, end of 2nd,
 //                    meta of 1st, meta of 2nd}, meta = id << 2 | kind
+//   backed[b]   u8   bit 0 / bit 1: the first / second range was inserted as backed memory
 // A lookup finds the last bucket whose base is <= addr, then reads one 32-byte record to
 // pick the range inside the bucket and to get its end, id and kind.
 #pragma once
@@ -39,6 +40,7 @@ struct DevTable {
     const uint32_t* split32;
     const PairRec* rec;
     const uint32_t* radix;  // validation search index, see below
+    const uint8_t* backed;  // per bucket: bit 0 / bit 1 = first / second range is backed memory
     uint64_t gmin;
     uint32_t nb;          // number of buckets (0 for an empty table)
     uint32_t shift;
@@ -142,8 +144,6 @@ __device__ inline void verdict_lane(const DevTable& t, uint64_t a, uint64_t len,
     classify_in_bucket(load_rec(t.rec + b), a, len < 1 ? 1 : len, v, owner);
 }
 
-// Wave-cooperative search for a wave-uniform address: each step compares 64 evenly spaced
-// splitters at once (ballot + popcount), shrinking the candidate range 64x per step.
 // Move a wave-uniform 64-bit value into scalar registers (readfirstlane works on 32-bit
 // halves and returns int: widen through uint32_t so no sign bits leak into the high half).
 __device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {

@@ -7,7 +7,8 @@
 //  * SINK: a denied access of width w at exact address A goes to the quarantine slot
 //    q + ((A mod 2^64) mod qsize), rounded down to a multiple of w (qsize a power of two);
 //  * REPORT: a denied access is performed at A itself when [A, A+w) lies inside one registered
-//    range of the handle's table (any kind), and stays suppressed otherwise;
+//    range of the handle's table (any kind) that was inserted as backed memory, and stays
+//    suppressed otherwise;
 //  * REMAP ("remap_or", kept safe: the target is a live user allocation, its own argument's):
 //    with lo' = lo rounded up to w and m the largest multiple of w not above hi - lo', the
 //    access goes to lo' + ((A - lo') mod m) rounded down to w; no binding leaves it suppressed.
@@ -42,8 +43,10 @@ __device__ inline uint8_t* redirect_to(const DevTable& t, const Redirect& r, Bin
     const int64_t bk = bucket_search_lane(t, a);
     if (bk < 0) return nullptr;
     const PairRec rec = load_rec(t.rec + bk);
-    const uint64_t end = rec.base1 <= a ? rec.end1 : rec.end0;
+    const bool second = rec.base1 <= a;
+    const uint64_t end = second ? rec.end1 : rec.end0;
     if (a >= end || (uint64_t)w > end - a) return nullptr;
+    if (!((t.backed[bk] >> (second ? 1 : 0)) & 1u)) return nullptr;  // no memory promised there
     return reinterpret_cast<uint8_t*>(a);
 }
 

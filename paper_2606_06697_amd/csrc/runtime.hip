@@ -27,6 +27,7 @@ struct Entry {
     uint64_t base, end;
     int32_t id;
     uint8_t kind;
+    uint8_t backed;  // inserted with AGILE_RANGE_BACKED (mapped memory, REPORT may touch it)
 };
 
 using agile::DeviceGuard;
@@ -41,6 +42,7 @@ struct Image {
     PairRec* rec = nullptr;
     uint32_t* radix = nullptr;
     uint4* nrec = nullptr;
+    uint8_t* backed = nullptr;       // per bucket: bit 0 first range backed, bit 1 second
     void* stage = nullptr;           // pinned staging the upload copies from
     hipEvent_t ready = nullptr;      // recorded after the upload into this image
     hipStream_t ready_stream = nullptr;
@@ -99,8 +101,11 @@ static size_t radix_offset(uint32_t cap_nb) {
 static size_t nrec_offset(uint32_t cap_nb) {
     return radix_offset(cap_nb) + (((size_t)MAX_RADIX * 4 + 63) / 64) * 64;
 }
-static size_t image_bytes(uint32_t cap_nb) {
+static size_t backed_offset(uint32_t cap_nb) {
     return nrec_offset(cap_nb) + (size_t)cap_nb * 16;
+}
+static size_t image_bytes(uint32_t cap_nb) {
+    return backed_offset(cap_nb) + (((size_t)cap_nb + 63) / 64) * 64;
 }
 
 static uint32_t bitlen(uint64_t x) {
@@ -245,10 +250,12 @@ static int upload(agile_rt* rt, hipStream_t s) {
     PairRec* rec = reinterpret_cast<PairRec*>(h + rec_offset(rt->cap_nb));
     uint32_t* radix = reinterpret_cast<uint32_t*>(h + radix_offset(rt->cap_nb));
     uint32_t* nrec = reinterpret_cast<uint32_t*>(h + nrec_offset(rt->cap_nb));
+    uint8_t* bk = h + backed_offset(rt->cap_nb);
     const auto& E = rt->entries;
     for (uint32_t b = 0; b < nb; ++b) {
         const Entry& e0 = E[2 * b];
         s64[b] = e0.base;
+        bk[b] = (uint8_t)(e0.backed | ((2 * b + 1 < n ? E[2 * b + 1].backed : 0) << 1));
         PairRec r;
         r.end0 = e0.end;
         r.meta0 = ((uint32_t)e0.id << 2) | e0.kind;
@@ -269,6 +276,7 @@ static int upload(agile_rt* rt, hipStream_t s) {
     t.split32 = im.split32;
     t.rec = im.rec;
     t.radix = im.radix;
+    t.backed = im.backed;
     t.nb = nb;
     t.compressed = 0;
     if (nb > 0) {
@@ -310,7 +318,8 @@ static int upload(agile_rt* rt, hipStream_t s) {
             hipMemcpyAsync(im.split32, s32, (size_t)nb * 4, hipMemcpyHostToDevice, s) != hipSuccess)
             return AGILE_EDEVICE;
         if (hipMemcpyAsync(im.rec, rec, (size_t)nb * sizeof(PairRec), hipMemcpyHostToDevice, s) !=
-            hipSuccess)
+                hipSuccess ||
+            hipMemcpyAsync(im.backed, bk, nb, hipMemcpyHostToDevice, s) != hipSuccess)
             return AGILE_EDEVICE;
     }
     if (t.narrow &&
@@ -406,6 +415,7 @@ int agile_rt_create(agile_rt** out, uint32_t capacity, int device) {
         im.rec = reinterpret_cast<PairRec*>(d + rec_offset(rt->cap_nb));
         im.radix = reinterpret_cast<uint32_t*>(d + radix_offset(rt->cap_nb));
         im.nrec = reinterpret_cast<uint4*>(d + nrec_offset(rt->cap_nb));
+        im.backed = d + backed_offset(rt->cap_nb);
         if (hipHostMalloc(&im.stage, rt->stage_bytes, hipHostMallocDefault) != hipSuccess ||
             hipEventCreateWithFlags(&im.ready, hipEventDisableTiming) != hipSuccess) {
             agile_rt_destroy(rt);
@@ -448,9 +458,15 @@ int agile_rt_destroy(agile_rt* rt) {
     return rc;
 }
 
+// kind: an AGILE_KIND_* value, optionally with AGILE_RANGE_BACKED
 static int check_range(uint64_t base, uint64_t size, uint32_t kind) {
-    if (kind > AGILE_KIND_MMIO || size < 1 || size > U64MAX - base) return AGILE_EINVAL;
+    const uint32_t k = kind & ~(uint32_t)AGILE_RANGE_BACKED;
+    if (k > AGILE_KIND_MMIO || size < 1 || size > U64MAX - base) return AGILE_EINVAL;
     return AGILE_OK;
+}
+static Entry make_entry(uint64_t base, uint64_t size, int32_t id, uint32_t kind) {
+    return Entry{base, base + size, id, (uint8_t)(kind & ~(uint32_t)AGILE_RANGE_BACKED),
+                 (uint8_t)((kind & AGILE_RANGE_BACKED) ? 1 : 0)};
 }
 
 int agile_rt_insert(agile_rt* rt, uint64_t base, uint64_t size, uint32_t kind, int32_t* out_id) {
@@ -466,7 +482,7 @@ int agile_rt_insert(agile_rt* rt, uint64_t base, uint64_t size, uint32_t kind, i
     if (it != E.begin() && std::prev(it)->end > base) return AGILE_EOVERLAP;
     if (it != E.end() && it->base < end) return AGILE_EOVERLAP;
     const int32_t id = rt->next_id++;
-    E.insert(it, Entry{base, end, id, (uint8_t)kind});
+    E.insert(it, make_entry(base, size, id, kind));
     rt->by_id[id] = base;
     rt->dirty = true;
     if (out_id) *out_id = id;
@@ -488,7 +504,7 @@ int agile_rt_insert_many(agile_rt* rt, const uint64_t* base, const uint64_t* siz
         return AGILE_ENOSPC;
     std::vector<Entry> add(n);
     for (uint32_t i = 0; i < n; ++i)
-        add[i] = Entry{base[i], base[i] + size[i], rt->next_id + (int32_t)i, kind[i]};
+        add[i] = make_entry(base[i], size[i], rt->next_id + (int32_t)i, kind[i]);
     std::vector<Entry> merged;
     merged.reserve(rt->entries.size() + n);
     std::vector<Entry> sorted_add = add;

@@ -22,6 +22,7 @@ AGILE_ENOENT, AGILE_ENOSPC, AGILE_EDEVICE, AGILE_EFAULTED = -4, -5, -6, -7
 AGILE_ETRAPPED, AGILE_ENOTSUP = -8, -9
 AP_IO, AP_MODULE, AP_USER = 0, 1, 2
 KIND_USER, KIND_PROTECTED, KIND_MMIO = 0, 1, 2
+RANGE_BACKED = 0x80                     # OR-ed into a kind: the range is mapped memory
 ALLOW, V_PROTECTED, V_STRADDLE, V_UNMAPPED, V_CROSS_ALLOC, V_INEXACT = 0, 1, 2, 3, 4, 5
 (POLICY_SUPPRESS_LOG, POLICY_SUPPRESS_ONLY, POLICY_TRAP, POLICY_SINK, POLICY_REPORT,
  POLICY_REMAP) = 0, 1, 2, 3, 4, 5
@@ -451,14 +452,17 @@ class RangeTable:
         except Exception:
             pass
 
-    def insert(self, base: int, size: int, kind: int = KIND_USER) -> int:
-        return agile_rt_insert(self.handle, base, size, kind)
+    def insert(self, base: int, size: int, kind: int = KIND_USER, backed: bool = False) -> int:
+        return agile_rt_insert(self.handle, base, size, kind | (RANGE_BACKED if backed else 0))
 
     def insert_tensor(self, t: torch.Tensor, kind: int = KIND_USER) -> int:
-        """Register a tensor's bytes as one range."""
-        return self.insert(t.data_ptr(), t.numel() * t.element_size(), kind)
+        """Register a tensor's bytes as one range (backed: a tensor's storage is mapped
+        device memory)."""
+        return self.insert(t.data_ptr(), t.numel() * t.element_size(), kind, backed=True)
 
-    def insert_many(self, base, size, kind):
+    def insert_many(self, base, size, kind, backed: bool = False):
+        if backed:
+            kind = torch.as_tensor(kind).to(torch.uint8) | RANGE_BACKED
         return agile_rt_insert_many(self.handle, base, size, kind)
 
     def remove(self, rid: int) -> None:

@@ -38,14 +38,14 @@ class Twin:
     def h(self):
         return self.rt.handle
 
-    def insert(self, base, size, kind):
+    def insert(self, base, size, kind, backed=False):
         try:
-            a = self.rt.insert(base, size, kind)
+            a = self.rt.insert(base, size, kind, backed)
         except self.g.AgileError:
             with pytest.raises(ValueError):   # the oracle rejects it too (OverlapError et al.)
-                self.ot.insert(base, size, kind)
+                self.ot.insert(base, size, kind, backed)
             raise
-        b = self.ot.insert(base, size, kind)
+        b = self.ot.insert(base, size, kind, backed)
         assert a == b
         return a
 

@@ -301,7 +301,8 @@ def test_redirecting_policies_full_size_gather():
     T = table.data_ptr()
     for ptr, size, kind in ((idx.data_ptr(), NI * 8, 0), (out.data_ptr(), NI * 4, 0),
                             (T, ROWS * 4, 0), (T + ROWS * 4, PAD, 1)):
-        assert dt.insert(ptr, size, kind) == ot.insert(ptr, size, kind)
+        # all four are device memory (the pad is the tail of gbuf), so REPORT may touch them
+        assert dt.insert(ptr, size, kind, backed=True) == ot.insert(ptr, size, kind, backed=True)
     g.agile_rt_set_quarantine(dt.handle, quar, QS)
     bad = (idx < 0) | (idx >= ROWS)
     ib = torch.nonzero(bad).flatten()

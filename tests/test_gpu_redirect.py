@@ -7,8 +7,9 @@ pointer argument, modulo that range's size (Section V-E, sink, report and remap_
 holds:
 a USER table/destination A, a protected canary P, an unregistered hole H, another USER
 allocation X, an index buffer I, a source S, an output C and the quarantine Q (not
-registered). Every registered range is backed by the arena, so REPORT only ever touches arena
-bytes. Values are small integers, so sums are exact in any order, and the whole arena,
+registered). Every registered range lies in the arena and is inserted as backed, so REPORT only
+ever touches arena bytes; one case registers P without that statement, and REPORT must then
+leave it alone. Values are small integers, so sums are exact in any order, and the whole arena,
 quarantine included, must equal the oracle's memory byte for byte. Within one call the denied
 accesses that reach the same quarantine slot or address are either all loads or all adds
 (their order is unspecified, as for duplicate indices of a plain scatter); under REMAP the
@@ -37,7 +38,7 @@ def layout(rb):
     return off, (o + 4095) // 4096 * 4096
 
 
-def setup(w, D, seed):
+def setup(w, D, seed, backed_p=True):
     need_gpu()
     rb = w * D
     off, size = layout(rb)
@@ -45,7 +46,7 @@ def setup(w, D, seed):
     tw = Twin(16)
     for k, kind in (("A", 0), ("P", 1), ("X", 0), ("I", 0), ("S", 0), ("C", 0)):
         lo, hi = off[k]
-        tw.insert(ar.addr(lo), hi - lo, kind)
+        tw.insert(ar.addr(lo), hi - lo, kind, backed=backed_p or k != "P")
     dt = np.float32 if w == 4 else np.float64
     rng = np.random.default_rng(seed)
     for k in ("A", "P", "H", "X", "S", "C"):
@@ -220,4 +221,37 @@ def test_remap_rounds_an_unaligned_binding_up():
     run_both(tw, ar, lambda: g.agile_guarded_triad(tw.h, a, C, X, 2.0, 600, G.REMAP),
              lambda: G.triad_loop(tw.ot, ar.mem, ol, tw.next_seq(), a, C, X, 2.0, 600, G.REMAP),
              ol, "remap, unaligned binding, denied stores")
+    tw.close()
+
+
+@pytest.mark.parametrize("w,D", [(4, 1), (8, 2)])
+def test_report_leaves_a_range_not_declared_backed_alone(w, D):
+    """P is registered as protected but not as backed: under REPORT denied loads from it read 0
+    and denied stores into it are dropped (P keeps its bytes), exactly as the oracle says; the
+    other registered ranges are still reported through."""
+    ar, tw, off, dt, rng = setup(w, D, 91 + w, backed_p=False)
+    g = tw.g
+    rb = w * D
+    A, I, S, C = (ar.addr(off[k][0]) for k in ("A", "I", "S", "C"))
+    ol = G.FaultLog()
+    n = 500
+    into_p = [ROWS + k for k in range(0, 4096 // rb, 9)]           # rows inside P
+    into_x = [ROWS + 8192 // rb + k for k in range(0, 8192 // rb, 13)]   # rows inside X
+    idx = rng.integers(0, ROWS, n).astype(np.int64)
+    pos = rng.choice(n, len(into_p) + len(into_x), replace=False)
+    idx[pos] = into_p + into_x
+    ar.write(off["I"][0], idx)
+    run_both(tw, ar, lambda: g.agile_guarded_gather(tw.h, C, A, rb, I, n, 0 if w == 4 else 1,
+                                                    G.REPORT),
+             lambda: G.gather_loop(tw.ot, ar.mem, ol, tw.next_seq(), C, A, rb, I, n, w,
+                                   G.REPORT), ol, "report gather, P not backed")
+    # scatter into P (dropped) and into X (performed), distinct rows
+    idx = rng.permutation(ROWS)[:n].astype(np.int64)
+    pos = rng.choice(n, len(into_p) + len(into_x), replace=False)
+    idx[pos] = into_p + into_x
+    ar.write(off["I"][0], idx)
+    run_both(tw, ar, lambda: g.agile_guarded_scatter(tw.h, A, rb, I, S, n, 0 if w == 4 else 1, 0,
+                                                     G.REPORT),
+             lambda: G.scatter_loop(tw.ot, ar.mem, ol, tw.next_seq(), A, rb, I, S, n, w, False,
+                                    G.REPORT), ol, "report scatter, P not backed")
     tw.close()

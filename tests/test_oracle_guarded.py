@@ -45,20 +45,24 @@ def scenario(seed):
     addr = {}
 
     def user(name, base, size):
-        t.insert(base, size, USER)
+        t.insert(base, size, USER, backed=True)
         mem.add(base, rng.integers(0, 256, size, dtype=np.uint8))
         addr[name] = (base, base + size)
 
     user("A", BASE, 512)
     user("B", BASE + 512, 384)                    # adjacent to A
-    t.insert(BASE + 896, 128, PROTECTED)           # canary, backed so we can check it
+    t.insert(BASE + 896, 128, PROTECTED, backed=True)   # canary, backed so we can check it
     mem.add(BASE + 896, np.full(128, 0xA5, np.uint8))
     addr["P"] = (BASE + 896, BASE + 1024)
     user("C", BASE + 2048, 1000)                   # hole [1024, 2048) before it
-    t.insert(BASE + 4096, 64, MMIO)
+    t.insert(BASE + 4096, 64, MMIO, backed=True)
     mem.add(BASE + 4096, np.full(64, 0x3C, np.uint8))    # backed (REPORT may touch it)
     addr["M"] = (BASE + 4096, BASE + 4160)
     user("I", BASE + 8192, 8 * 64)                 # index buffer
+    # registered but not declared backed, and with no memory in the model: any read or write
+    # there raises, so every policy must leave it alone
+    t.insert(BASE + 6144, 256, PROTECTED)
+    addr["U"] = (BASE + 6144, BASE + 6400)
     return t, mem, addr
 
 
@@ -576,6 +580,37 @@ def test_report_performs_only_inside_registered_ranges():
     m = copy.deepcopy(mem)
     G.copy_loop(t, m, G.FaultLog(), 0, P0, A0, 8, G.REPORT)
     assert m.read(P0, 8) == m.read(A0, 8) != bytes([0xA5] * 8)
+
+
+def test_report_leaves_a_range_not_declared_backed_alone():
+    """A registered range that was not inserted as backed may have no memory behind it: under
+    REPORT a denied load there reads 0 and a denied store there is dropped (the memory model
+    holds nothing at U, so touching it would raise), with the log of SUPPRESS_LOG."""
+    t, mem, addr = scenario(8)
+    A0, U0 = addr["A"][0], addr["U"][0]
+    rows = [1, (U0 - A0) // 4 + 3, 7, (U0 - A0) // 4 + 60]
+    logs = []
+    for pol in (G.REPORT, G.SUPPRESS_LOG):
+        m = copy.deepcopy(mem)
+        idx_ptr = _write_idx(m, addr, rows)
+        log = RecordingLog()
+        G.gather_loop(t, m, log, 0, addr["C"][0], A0, 4, idx_ptr, len(rows), 4, pol)
+        got = [m.read(addr["C"][0] + 4 * k, 4) for k in range(len(rows))]
+        assert got[1] == got[3] == bytes(4)
+        assert got[0] == m.read(A0 + 4, 4) and got[2] == m.read(A0 + 28, 4)
+        logs.append((log.count, log.first))
+    assert logs[0] == logs[1] and logs[0][0] == 2
+    # a copy into U and out of U: both directions suppressed, the log counts every byte
+    for dst, src in ((U0 + 16, A0), (A0 + 64, U0 + 8)):
+        m = copy.deepcopy(mem)
+        before = m.read(A0, 512)
+        log = G.FaultLog()
+        G.copy_loop(t, m, log, 0, dst, src, 8, G.REPORT)
+        assert log.count == 8                   # one denied access per byte
+        if dst == A0 + 64:
+            assert m.read(A0 + 64, 8) == bytes(8)
+        else:
+            assert m.read(A0, 512) == before
 
 
 def test_sink_with_a_zero_quarantine_and_no_denied_store_equals_suppress():

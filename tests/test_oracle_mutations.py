@@ -45,6 +45,7 @@ GUARD_CHECKS = ([PG.test_access_straddling_the_allocation_end_is_denied,
                  PG.test_trap_policy_retires_on_a_violation_only, PG.test_sink_by_hand,
                  PG.test_sink_aligns_the_slot_to_the_access_width,
                  PG.test_report_performs_only_inside_registered_ranges,
+                 PG.test_report_leaves_a_range_not_declared_backed_alone,
                  PG.test_sink_with_a_zero_quarantine_and_no_denied_store_equals_suppress,
                  PG.test_sink_scatter_add_accumulates_in_the_quarantine,
                  PG.test_remap_copy_from_a_short_allocation_repeats_it,
@@ -262,6 +263,15 @@ def _target_report_everywhere(self, A, w, bind=(0, 0)):
     return _ORIG_TARGET(self, A, w, bind)
 
 
+def _target_report_ignores_backing(self, A, w, bind=(0, 0)):
+    if self.policy == G.REPORT:
+        ent = self.t.owner_entry(A)
+        if ent is not None and 0 <= A and A + w <= ent[1]:
+            return A
+        return None
+    return _ORIG_TARGET(self, A, w, bind)
+
+
 def _target_remap_by_size(self, A, w, bind=(0, 0)):
     if self.policy == G.REMAP and bind[1] > bind[0]:
         lo, hi = bind
@@ -284,6 +294,7 @@ _ORIG_TARGET = G._Denier.target
 DENIER_MUTANTS = {
     "sink slot not aligned to the access width": ("target", _target_unaligned),
     "report performs outside registered ranges": ("target", _target_report_everywhere),
+    "report performs in ranges not declared backed": ("target", _target_report_ignores_backing),
     "remap wraps by the allocation size, not whole elements": ("target", _target_remap_by_size),
     "redirected stores dropped": ("store", _store_dropped),
     "redirected scatter-add overwrites": ("add", _add_overwrites),
