@@ -58,6 +58,55 @@ void drop_events(std::vector<hipEvent_t>& v) {
     v.clear();
 }
 
+// Device scratch of the sorted scatter-add, grown on demand and released in stream order: the
+// stream of the call that grows it first waits (on the device) for every other stream that used
+// the old buffer, then frees it and allocates the new one on that stream. Nothing waits on the
+// host, and launches on unrelated streams are not held up.
+struct StreamScratch {
+    void* buf = nullptr;
+    size_t cap = 0;
+    std::vector<hipStream_t> users;  // streams that launched with buf
+
+    // null when it cannot grow (the caller then takes a path without scratch)
+    void* get(size_t need, hipStream_t s) {
+        if (need <= cap) {
+            if (std::find(users.begin(), users.end(), s) == users.end()) users.push_back(s);
+            return buf;
+        }
+        if (buf) {
+            for (hipStream_t o : users) {
+                if (o == s) continue;
+                hipEvent_t e;
+                if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+                const bool ok = hipEventRecord(e, o) == hipSuccess && hipStreamWaitEvent(s, e, 0) == hipSuccess;
+                (void)hipEventDestroy(e);
+                if (!ok) return nullptr;
+            }
+            if (hipFreeAsync(buf, s) != hipSuccess) return nullptr;
+            buf = nullptr;
+            cap = 0;
+            users.clear();
+        }
+        const size_t want = need + need / 4;
+        if (hipMallocAsync(&buf, want, s) != hipSuccess) {
+            (void)hipGetLastError();
+            buf = nullptr;
+            return nullptr;
+        }
+        cap = want;
+        users.assign(1, s);
+        return buf;
+    }
+
+    // once no queued work can use it any more
+    void release() {
+        if (buf) (void)hipFreeAsync(buf, nullptr);
+        buf = nullptr;
+        cap = 0;
+        users.clear();
+    }
+};
+
 }  // namespace
 
 struct agile_rt {
@@ -86,9 +135,7 @@ struct agile_rt {
     uint64_t q_bytes = 0;
     bool retired = false;                 // retired by a TRAP-policy violation
     std::vector<hipStream_t> streams_used;  // streams that launched with the current image
-    // sort scratch of the scatter-add (grown on demand)
-    void* sa_scratch = nullptr;
-    size_t sa_bytes = 0;
+    StreamScratch sa;  // sort scratch of the scatter-add (grown on demand)
 };
 
 // Image layout: split64 | split32 | (64-byte aligned) rec | radix
@@ -453,7 +500,9 @@ int agile_rt_destroy(agile_rt* rt) {
     if (rt->hlog) (void)hipHostFree(rt->hlog);
     if (rt->htrap) (void)hipHostFree(rt->htrap);
     if (rt->dmem) (void)hipFree(rt->dmem);
-    if (rt->sa_scratch) (void)hipFree(rt->sa_scratch);
+    const bool had_scratch = rt->sa.buf != nullptr;
+    rt->sa.release();  // the device is idle (synchronized above)
+    if (had_scratch && hipStreamSynchronize(nullptr) != hipSuccess) rc = AGILE_EDEVICE;
     delete rt;
     return rc;
 }
@@ -653,26 +702,6 @@ static int trap_end(agile_rt* rt, int policy, hipStream_t s) {
     return AGILE_ETRAPPED;
 }
 
-// Scratch of the sorted scatter-add, grown on demand; the old buffer is released only after the
-// device has finished every launch that may still use it. Returns null when it cannot grow (the
-// caller then takes the chunk path, which needs no scratch).
-static void* grow_scratch(void*& buf, size_t& cap, size_t need) {
-    if (need <= cap) return buf;
-    if (buf) {
-        if (hipDeviceSynchronize() != hipSuccess) return nullptr;
-        (void)hipFree(buf);
-        buf = nullptr;
-        cap = 0;
-    }
-    const size_t want = need + need / 4;
-    if (hipMalloc(&buf, want) != hipSuccess) {
-        buf = nullptr;
-        return nullptr;
-    }
-    cap = want;
-    return buf;
-}
-
 // Binding of a pointer argument of a guarded call: the USER range containing p, from the host
 // copy of the table (the state the launch is ordered after), or the empty interval.
 static Bind host_bind(const agile_rt* rt, uint64_t p) {
@@ -815,7 +844,7 @@ int agile_guarded_scatter(agile_rt* rt, void* d_dst, uint64_t row_bytes, const i
     const Bind b[3] = {host_bind(rt, (uint64_t)d_idx), host_bind(rt, (uint64_t)d_src),
                        host_bind(rt, (uint64_t)d_dst)};
     void* scr = (accumulate && n >= SORT_MIN_N)
-                    ? grow_scratch(rt->sa_scratch, rt->sa_bytes, scatter_add_scratch_bytes(n))
+                    ? rt->sa.get(scatter_add_scratch_bytes(n), s)
                     : nullptr;
     if (redirecting(policy)) {
         const RowsGuard full = rows_guard(b[0], b[1], b[2], (uint64_t)d_idx, (uint64_t)d_src,
@@ -1111,15 +1140,14 @@ int agile_unguarded_scatter(void* d_dst, uint64_t row_bytes, const int64_t* d_id
     if (n && (!d_dst || !d_src || !d_idx)) return AGILE_EINVAL;
     void* scr = nullptr;
     if (accumulate && n >= SORT_MIN_N) {
-        // one scratch buffer per device for the unguarded twin (its calls on a device are
-        // ordered by the caller)
+        // one scratch buffer per device for the unguarded twin, kept until the process ends
         static std::mutex mu;
-        static std::vector<std::pair<void*, size_t>> per_dev;
+        static std::vector<StreamScratch> per_dev;
         int dev = 0;
         (void)hipGetDevice(&dev);
         std::lock_guard<std::mutex> lk(mu);
-        if ((size_t)dev >= per_dev.size()) per_dev.resize(dev + 1, {nullptr, 0});
-        scr = grow_scratch(per_dev[dev].first, per_dev[dev].second, scatter_add_scratch_bytes(n));
+        if ((size_t)dev >= per_dev.size()) per_dev.resize(dev + 1);
+        scr = per_dev[dev].get(scatter_add_scratch_bytes(n), static_cast<hipStream_t>(stream));
     }
     return launch_scatter(false, DevTable{}, nullptr, nullptr, d_dst, row_bytes, d_idx, d_src, n, w,
                           accumulate, 0, 0, scr, current_info(),
