@@ -43,7 +43,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-extras", action="store_true",
                    help="skip the embedding and batched-launch measurements")
-    p.add_argument("--serve-seconds", type=float, default=5.0,
+    p.add_argument("--serve-seconds", type=float, default=60.0,
                    help="length of the serving-loop run (0 skips it)")
     p.add_argument("--counters-pass", action="store_true",
                    help="only launch each large-table kernel a few times, plus a plain 1 GiB copy "
@@ -530,12 +530,16 @@ def bench_embedding(g, args):
     assert int(f["count"]) == nbad * D * calls_guarded, (int(f["count"]), nbad)
     t.close()
     med = {k: float(np.median(v)) for k, v in ts.items()}
-    fwd_bytes = N * (8 + 2 * rb)
+    # bytes that must cross HBM: the index, each distinct row once (repeated Zipf rows are
+    # served by the caches), the output; backward: dY, the index, a read and a write of every
+    # distinct destination row
+    fwd_bytes = N * (8 + rb) + distinct * rb
     bwd_bytes = N * (8 + rb) + distinct * 2 * rb
     out = {"workload": "1048576x256 fp32 table, 2^20 Zipf(1.1) idx, 0.01% hostile",
            "kernel_ms": {k: round(v, 4) for k, v in med.items()},
            "forward_gbps": round(fwd_bytes / med["forward"] / 1e6, 1),
            "forward_unguarded_gbps": round(fwd_bytes / med["forward_unguarded"] / 1e6, 1),
+           "forward_rows_per_s": round(N / (med["forward"] / 1e3), 1),
            "backward_gbps": round(bwd_bytes / med["backward"] / 1e6, 1),
            "backward_unguarded_gbps": round(bwd_bytes / med["backward_unguarded"] / 1e6, 1),
            "distinct_rows": distinct, "hostile_idx": nbad,
@@ -685,6 +689,18 @@ def cpu_pool_validate(tb, qs, procs):
     return wall
 
 
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or the machine type."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
 def cpu_baseline(tb, step_bytes, nq):
     """Time the oracle (as it stands) on a bounded sample of the same workload (about 10 s of
     single-thread CPU work) and scale each part to its full size."""
@@ -744,9 +760,8 @@ def cpu_baseline(tb, step_bytes, nq):
             "kind": "oracle",
             "sample": f"validate {nsv} queries on the same 65536-range table ({tv:.2f} s), "
                       f"triad {nst} elems ({ttr:.2f} s), gather {nsg} idx over {rows} rows "
-                      f"({tgt:.2f} s); each scaled to its full size; host "
-                      f"{platform.processor() or platform.machine()}, {os.cpu_count()} cpus "
-                      "visible, numpy single-threaded",
+                      f"({tgt:.2f} s); each scaled to its full size; host CPU "
+                      f"{cpu_model()}, {os.cpu_count()} cpus visible, numpy single-threaded",
             "validations_per_s": round(nsv / tv, 1),
             "pool_validate": pool}
 

@@ -4,8 +4,9 @@ Forward: ``Y[i, :] = W[idx[i], :]`` through ``agile_guarded_gather``: a row whos
 outside W's own allocation (a hostile index aimed at a protected range, a hole, or another
 allocation) reads zeros and is counted in the table's fault log. Backward:
 ``dW[r, :] = sum of dY[i, :] over allowed i with idx[i] = r`` through ``agile_guarded_scatter``
-with accumulation (chunk-sorted, one atomic row-update per run of equal rows); contributions
-aimed outside dW are dropped and counted. Both run on the current torch stream.
+with accumulation (calls of 32,768 rows or more radix-sort their destination rows and sum each
+run of equal rows once; smaller calls sort chunks of 2,048 rows in LDS and add each run with one
+atomic row update); contributions aimed outside dW are dropped and counted. Both run on the current torch stream.
 
 The guard binds every pointer argument to its own USER range, so the temporaries this function
 creates (the output Y, the incoming gradient dY and the gradient dW) are registered in the

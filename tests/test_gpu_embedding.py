@@ -1,4 +1,5 @@
-"""Guarded embedding (forward gather, chunk-sorted scatter-add backward) against the oracle."""
+"""Guarded embedding (forward gather, sorted guarded scatter-add backward: radix-sorted for
+large calls, chunk-sorted for small ones) against the oracle."""
 import numpy as np
 import pytest
 import torch
