@@ -55,7 +55,8 @@ enum {
     AGILE_ENOSPC = -5,    /* table at capacity, or the id space (2^30 ids) is used up */
     AGILE_EDEVICE = -6,   /* a HIP runtime call or kernel launch failed */
     AGILE_EFAULTED = -7,  /* fault log is non-empty ("poison" surfaces here) */
-    AGILE_ETRAPPED = -8   /* the handle was retired by a violation under AGILE_POLICY_TRAP */
+    AGILE_ETRAPPED = -8,  /* the handle was retired by a violation under AGILE_POLICY_TRAP */
+    AGILE_E2BIG = -10     /* more rows than agile_guarded_scatter_add_noalloc's fixed scratch holds */
 };
 
 /* Range kinds (Table I): user allocations, protected module/service memory, MMIO. */
@@ -440,6 +441,22 @@ int agile_server_run(agile_server* sv, agile_request* reqs, const uint64_t* out_
                      const double* revoke_s, uint32_t nrevoke, const uint8_t* record,
                      uint8_t* rec_buf, const uint64_t* rec_off, double* latency_s,
                      double* launch_s, agile_req_result* results, agile_server_stats* stats);
+
+/* ---- scatter-add without allocation ---------------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc. Same operation, arguments, policies and errors as
+ * agile_guarded_scatter with accumulate = 1, but the sort scratch of its large calls is a fixed
+ * array inside the library (AGILE_NOALLOC_SCRATCH_BYTES, one copy per GPU, held until the
+ * process ends) instead of a buffer the handle grows with hipMallocAsync; the call allocates no
+ * device memory. n above AGILE_NOALLOC_MAX_ROWS returns AGILE_E2BIG before anything is queued.
+ * Every call on one GPU shares that GPU's array and leaves its contents behind (each call sets
+ * up what it reads): calls that may overlap on one GPU (other streams, other threads) race on
+ * it and give wrong sums, so order them on one stream. */
+#define AGILE_NOALLOC_MAX_ROWS (1u << 20)
+#define AGILE_NOALLOC_SCRATCH_BYTES (17u << 20)
+int agile_guarded_scatter_add_noalloc(agile_rt* rt, void* d_dst, uint64_t row_bytes,
+                                      const int64_t* d_idx, const void* d_src, uint64_t n,
+                                      int dtype, int policy, void* stream);
 
 /* Static text for a status code. */
 const char* agile_strerror(int code);

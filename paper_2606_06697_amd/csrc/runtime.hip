@@ -7,6 +7,7 @@
 // to wait for its earlier work; the pinned staging buffer is reused only after its previous
 // upload completed. Guarded calls take consecutive sequence numbers (the first-fault order).
 #include <algorithm>
+#include <atomic>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
@@ -417,9 +418,42 @@ const char* agile_strerror(int code) {
         case AGILE_EFAULTED: return "guarded access denied (fault log not empty)";
         case AGILE_ETRAPPED: return "handle retired by a violation under the trap policy";
         case AGILE_ENOTSUP: return "the device does not support virtual memory management";
+        case AGILE_E2BIG: return "more rows than the no-allocation scatter-add's fixed scratch holds";
         default: return "unknown status";
     }
 }
+
+}  // extern "C"
+
+// ---- fixed scratch of the no-allocation scatter-add ------------------------------------
+// One copy per GPU (a device global, held until the process ends). In host code the name only
+// stands in for the symbol: kernels get the address hipGetSymbolAddress reports for the device.
+static __device__ __align__(256) unsigned char scratch[AGILE_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+std::atomic<void*> g_scratch_ptr[NOALLOC_MAX_DEVICES];  // device address of `scratch`, per device
+}  // namespace
+
+// The device address of `scratch` on `device`, looked up once with that device current (the
+// caller makes it current); null if the lookup failed.
+static void* noalloc_scratch(int device) {
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return nullptr;
+    void* p = g_scratch_ptr[device].load(std::memory_order_acquire);
+    if (p) return p;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    p = g_scratch_ptr[device].load(std::memory_order_relaxed);
+    if (p) return p;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    g_scratch_ptr[device].store(p, std::memory_order_release);
+    return p;
+}
+
+extern "C" {
 
 int agile_rt_create(agile_rt** out, uint32_t capacity, int device) {
     if (!out || capacity < 1 || capacity > MAX_CAPACITY) return AGILE_EINVAL;
@@ -441,6 +475,9 @@ int agile_rt_create(agile_rt** out, uint32_t capacity, int device) {
     rt->info.num_cu = p.multiProcessorCount;
     rt->info.lds_per_block = p.sharedMemPerBlock;
     rt->info.lds_per_cu = p.maxSharedMemoryPerMultiProcessor;
+    // set-up of the device: the no-allocation scatter-add's scratch address (looked up again by
+    // that entry point if this fails)
+    (void)noalloc_scratch(device);
     rt->lds_budget = 160 * 1024;
     if (const char* e = std::getenv("AGILE_LDS_BUDGET")) {
         long v = std::strtol(e, nullptr, 10);
@@ -822,9 +859,11 @@ int agile_guarded_gather(agile_rt* rt, void* d_out, const void* d_table, uint64_
     return trap_end(rt, policy, s);
 }
 
-int agile_guarded_scatter(agile_rt* rt, void* d_dst, uint64_t row_bytes, const int64_t* d_idx,
-                          const void* d_src, uint64_t n, int dtype, int accumulate, int policy,
-                          void* stream) {
+// Guarded scatter / scatter-add. noalloc: the sort scratch is the fixed device array `scratch`
+// (the caller checked that n fits it) instead of the handle's growing buffer.
+static int scatter_impl(agile_rt* rt, void* d_dst, uint64_t row_bytes, const int64_t* d_idx,
+                        const void* d_src, uint64_t n, int dtype, int accumulate, int policy,
+                        void* stream, bool noalloc) {
     if (!rt || !policy_ok(policy) || (accumulate != 0 && accumulate != 1)) return AGILE_EINVAL;
     if (rt->retired) return AGILE_ETRAPPED;
     Redirect rd;
@@ -836,6 +875,13 @@ int agile_guarded_scatter(agile_rt* rt, void* d_dst, uint64_t row_bytes, const i
     DeviceGuard dg(rt->device);
     if (!dg.ok) return AGILE_EDEVICE;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool sort = accumulate && n >= SORT_MIN_N;
+    void* fixed = nullptr;
+    if (noalloc && sort) {
+        if (scatter_add_scratch_bytes(n) > AGILE_NOALLOC_SCRATCH_BYTES) return AGILE_E2BIG;
+        fixed = noalloc_scratch(rt->device);
+        if (!fixed) return AGILE_EDEVICE;
+    }
     rc = prepare(rt, s);
     if (rc != AGILE_OK) return rc;
     rc = trap_begin(rt, policy, s);
@@ -843,9 +889,7 @@ int agile_guarded_scatter(agile_rt* rt, void* d_dst, uint64_t row_bytes, const i
     const unsigned long long seq = rt->seq++;
     const Bind b[3] = {host_bind(rt, (uint64_t)d_idx), host_bind(rt, (uint64_t)d_src),
                        host_bind(rt, (uint64_t)d_dst)};
-    void* scr = (accumulate && n >= SORT_MIN_N)
-                    ? rt->sa.get(scatter_add_scratch_bytes(n), s)
-                    : nullptr;
+    void* scr = !sort ? nullptr : (noalloc ? fixed : rt->sa.get(scatter_add_scratch_bytes(n), s));
     if (redirecting(policy)) {
         const RowsGuard full = rows_guard(b[0], b[1], b[2], (uint64_t)d_idx, (uint64_t)d_src,
                                           (uint64_t)d_dst, n, row_bytes, w);
@@ -864,6 +908,21 @@ int agile_guarded_scatter(agile_rt* rt, void* d_dst, uint64_t row_bytes, const i
         return AGILE_EDEVICE;
     }
     return trap_end(rt, policy, s);
+}
+
+int agile_guarded_scatter(agile_rt* rt, void* d_dst, uint64_t row_bytes, const int64_t* d_idx,
+                          const void* d_src, uint64_t n, int dtype, int accumulate, int policy,
+                          void* stream) {
+    return scatter_impl(rt, d_dst, row_bytes, d_idx, d_src, n, dtype, accumulate, policy, stream,
+                        false);
+}
+
+int agile_guarded_scatter_add_noalloc(agile_rt* rt, void* d_dst, uint64_t row_bytes,
+                                      const int64_t* d_idx, const void* d_src, uint64_t n,
+                                      int dtype, int policy, void* stream) {
+    if (!rt) return AGILE_EINVAL;
+    if (n > AGILE_NOALLOC_MAX_ROWS) return AGILE_E2BIG;
+    return scatter_impl(rt, d_dst, row_bytes, d_idx, d_src, n, dtype, 1, policy, stream, true);
 }
 
 int agile_fault_log_read(agile_rt* rt, agile_fault* out, int clear, void* stream) {

@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libagile_guard.so")
 
 AGILE_OK, AGILE_EINVAL, AGILE_ENOMEM, AGILE_EOVERLAP = 0, -1, -2, -3
 AGILE_ENOENT, AGILE_ENOSPC, AGILE_EDEVICE, AGILE_EFAULTED = -4, -5, -6, -7
-AGILE_ETRAPPED, AGILE_ENOTSUP = -8, -9
+AGILE_ETRAPPED, AGILE_ENOTSUP, AGILE_E2BIG = -8, -9, -10
+NOALLOC_MAX_ROWS = 1 << 20
 AP_IO, AP_MODULE, AP_USER = 0, 1, 2
 KIND_USER, KIND_PROTECTED, KIND_MMIO = 0, 1, 2
 RANGE_BACKED = 0x80                     # OR-ed into a kind: the range is mapped memory
@@ -83,6 +84,7 @@ _SIGS = {
     "agile_guarded_triad": (_int, [_vp, _vp, _vp, _vp, ctypes.c_float, _u64, _int, _vp]),
     "agile_guarded_gather": (_int, [_vp, _vp, _vp, _u64, _vp, _u64, _int, _int, _vp]),
     "agile_guarded_scatter": (_int, [_vp, _vp, _u64, _vp, _vp, _u64, _int, _int, _int, _vp]),
+    "agile_guarded_scatter_add_noalloc": (_int, [_vp, _vp, _u64, _vp, _vp, _u64, _int, _int, _vp]),
     "agile_fault_log_read": (_int, [_vp, ctypes.POINTER(agile_fault), _int, _vp]),
     "agile_unguarded_copy": (_int, [_vp, _vp, _u64, _vp]),
     "agile_unguarded_triad": (_int, [_vp, _vp, _vp, ctypes.c_float, _u64, _vp]),
@@ -249,6 +251,13 @@ def agile_guarded_scatter(rt: int, dst, row_bytes: int, idx, src, n: int, dtype:
     _check(lib().agile_guarded_scatter(rt, _ptr(dst), row_bytes, _ptr(idx), _ptr(src), n, dtype,
                                        accumulate, policy, _stream(stream)),
            "agile_guarded_scatter")
+
+
+def agile_guarded_scatter_add_noalloc(rt: int, dst, row_bytes: int, idx, src, n: int,
+                                      dtype: int = 0, policy: int = 0, stream=None) -> None:
+    _check(lib().agile_guarded_scatter_add_noalloc(rt, _ptr(dst), row_bytes, _ptr(idx), _ptr(src),
+                                                   n, dtype, policy, _stream(stream)),
+           "agile_guarded_scatter_add_noalloc")
 
 
 def agile_fault_log_read(rt: int, clear: bool = False, stream=None):
