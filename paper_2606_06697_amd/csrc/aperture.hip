@@ -1,15 +1,20 @@
 // Fixed address apertures (AgileOS Section IV-E, Table I), built with HIP's virtual memory calls
-// the way Section V-A builds them with CUDA's: read the minimum allocation granularity, reserve
-// the I/O, module and user apertures back to back in Table I's order, attach physical memory
-// (create a handle, map it, grant the device read/write access), and record each allocation
-// (base, requested size) in a range table.
+// the way Section V-A builds them with CUDA's: read the allocation granularity, reserve the I/O,
+// module and user apertures back to back in Table I's order, and attach physical memory to each
+// allocation as it is made (create a handle, map it into its aperture, grant the device
+// read/write access), recording the allocation's base and requested size in a range table.
 //
-// The paper attaches memory per allocation. This HIP runtime resolves a second live mapping
-// inside one reservation to the first mapping's handle, so granting access to it fails or
-// would not reach it. Each aperture is therefore its own reservation with at most one mapping:
-// a backing of a size fixed at creation, mapped at the aperture's start, from which
-// allocations are carved (lowest fit, in granules). Allocation and release make no HIP call
-// other than the release's device synchronization.
+// Reservations. Every free run of an aperture is one reservation, and so is every allocation:
+// an allocation releases the free run it is taken from and reserves, at the same addresses, its
+// own range and what is left of the run; a release merges its range back with its free
+// neighbours the same way. The aperture's addresses therefore stay reserved at all times, and
+// each reservation holds at most one mapping. Inside one large reservation this runtime refuses
+// device access to some mappings depending on what was mapped before them (in a 1 TiB
+// reservation, 4 KiB mapped right after 1 MiB + 4 KiB or after 2 MiB: hipMemMap succeeds,
+// hipMemSetAccess fails with invalid argument and hipMemGetAccess reports no access; the same
+// pair in a 1 GiB reservation works). Every allocation's access is also read back (first and
+// last page) before the allocation is handed out, so memory without access never reaches a
+// kernel.
 //
 // The coarse check of the Fig. 2 guard then needs only the four aperture bounds: a streaming
 // kernel classifies (addr, len) queries with a few compares each. It reads 16 bytes and writes
@@ -30,19 +35,21 @@ using agile::DeviceGuard;
 
 struct agile_aperture {
     struct Alloc {
-        uint64_t bytes;  // carved bytes (the request rounded up to the granularity)
+        uint64_t bytes;  // mapped and reserved bytes (the request rounded up to the granularity)
         int region;
-        agile_rt* rt;  // table the allocation is registered in, or null
+        agile_rt* rt;    // table the allocation is registered in, or null
         int32_t id;
+        hipMemGenericAllocationHandle_t h;
     };
     int device = 0;
-    uint64_t gran = 0;
+    uint64_t gran = 0;   // the runtime's minimum allocation granularity
     bool user_hint = false;  // placed at a base address the caller asked for
+    bool broken = false;     // a failed re-reservation left part of an aperture unreserved
     uint64_t b[4] = {0, 0, 0, 0};
-    bool reserved[3] = {false, false, false};
-    uint64_t backed[3] = {0, 0, 0};  // bytes mapped at the start of each aperture
-    hipMemGenericAllocationHandle_t h[3] = {};
-    agile::VaRanges va[3];
+    uint64_t budget[3] = {0, 0, 0};  // most physical bytes each aperture may hold mapped
+    uint64_t mapped[3] = {0, 0, 0};  // physical bytes mapped now
+    hipMemAllocationProp prop{};
+    agile::VaRanges va[3];  // free runs, each one reservation
     std::map<uint64_t, Alloc> allocs;  // by address
 };
 
@@ -113,53 +120,72 @@ static uint32_t kind_of(int region) {
                                                                : AGILE_KIND_MMIO;
 }
 
-// Undo what create set up: unmap and release each aperture's backing, then free its
-// reservation. Failures are cleared from the runtime's last-error state, which later launch
-// checks read; the return value says whether everything was released.
+// Unmap and release one allocation's memory (the device must be done with it).
+static bool unmap_alloc(const agile_aperture::Alloc& a, uint64_t addr) {
+    bool ok = hipMemUnmap(reinterpret_cast<void*>(addr), a.bytes) == hipSuccess;
+    ok &= hipMemRelease(a.h) == hipSuccess;
+    if (!ok) (void)hipGetLastError();
+    return ok;
+}
+
+// Reserve exactly [s, e): true when the runtime grants that address.
+static bool reserve_exact(uint64_t s, uint64_t e, uint64_t align) {
+    void* p = nullptr;
+    const hipError_t r = hipMemAddressReserve(&p, e - s, align, reinterpret_cast<void*>(s), 0);
+    if (r == hipSuccess && reinterpret_cast<uint64_t>(p) == s) return true;
+    if (r == hipSuccess) (void)hipMemAddressFree(p, e - s);
+    (void)hipGetLastError();
+    return false;
+}
+
+static bool release(uint64_t s, uint64_t e) {
+    const bool ok = hipMemAddressFree(reinterpret_cast<void*>(s), e - s) == hipSuccess;
+    if (!ok) (void)hipGetLastError();
+    return ok;
+}
+
+// Replace the reservations [s, e) by the reservations [s, m) and [m, e) (s < m <= e; an empty
+// piece is not reserved). On failure the original reservation is restored if the runtime still
+// grants it; otherwise the aperture is marked broken.
+static bool split_run(agile_aperture* ap, uint64_t s, uint64_t m, uint64_t e) {
+    if (!release(s, e)) return false;
+    const bool a = reserve_exact(s, m, ap->gran);
+    const bool b = a && (m == e || reserve_exact(m, e, ap->gran));
+    if (b) return true;
+    if (a) (void)release(s, m);
+    if (!reserve_exact(s, e, ap->gran)) ap->broken = true;
+    return false;
+}
+
+// Free the reservations create made. Failures are cleared from the runtime's last-error state,
+// which later launch checks read; the return value says whether everything was released.
 static bool teardown(agile_aperture* ap) {
     bool ok = true;
     for (int k = 0; k < 3; ++k) {
-        void* p = reinterpret_cast<void*>(ap->b[k]);
-        if (ap->backed[k]) {
-            ok &= hipMemUnmap(p, ap->backed[k]) == hipSuccess;
-            ok &= hipMemRelease(ap->h[k]) == hipSuccess;
-            ap->backed[k] = 0;
-        }
-        if (ap->reserved[k]) {
-            // The HIP runtime may refuse to release a reservation placed at an address the
-            // caller asked for; that address range then stays reserved (no memory) until the
-            // process ends.
-            const bool freed = hipMemAddressFree(p, ap->b[k + 1] - ap->b[k]) == hipSuccess;
-            ok &= freed || ap->user_hint;
-            ap->reserved[k] = false;
-        }
+        // The HIP runtime may refuse to release a reservation placed at an address the caller
+        // asked for; that address range then stays reserved (no memory) until the process ends.
+        for (const auto& [fs, fe] : ap->va[k].free_) ok &= release(fs, fe) || ap->user_hint;
+        ap->va[k].free_.clear();
     }
     (void)hipGetLastError();
     return ok;
 }
 
-// Reserve the three apertures back to back from b0 (each at its requested address); false,
-// with nothing left reserved, when the runtime places any of them elsewhere.
+// Reserve the three apertures back to back from b0 (each at its requested address, each one
+// free run); false, with nothing left reserved, when the runtime places any of them elsewhere.
 static bool reserve_at(agile_aperture* ap, uint64_t b0, const uint64_t* sz) {
     uint64_t at = b0;
     for (int k = 0; k < 3; ++k) {
-        void* p = nullptr;
-        const hipError_t e = hipMemAddressReserve(&p, sz[k], ap->gran, reinterpret_cast<void*>(at), 0);
-        if (e == hipSuccess && reinterpret_cast<uint64_t>(p) != at) (void)hipMemAddressFree(p, sz[k]);
-        if (e != hipSuccess || reinterpret_cast<uint64_t>(p) != at) {
-            (void)hipGetLastError();
-            for (int j = 0; j < k; ++j) {
-                (void)hipMemAddressFree(reinterpret_cast<void*>(ap->b[j]), sz[j]);
-                ap->reserved[j] = false;
-            }
+        if (!reserve_exact(at, at + sz[k], ap->gran)) {
+            for (int j = 0; j < k; ++j) (void)release(ap->b[j], ap->b[j + 1]);
             (void)hipGetLastError();
             return false;
         }
         ap->b[k] = at;
-        ap->reserved[k] = true;
+        ap->b[k + 1] = at + sz[k];
         at += sz[k];
     }
-    ap->b[3] = at;
+    for (int k = 0; k < 3; ++k) ap->va[k].reset(ap->b[k], ap->b[k + 1]);
     return true;
 }
 
@@ -170,12 +196,11 @@ using namespace agile;
 extern "C" {
 
 int agile_aperture_create(agile_aperture** out, int device, const uint64_t* sizes,
-                          const uint64_t* backed, uint64_t base_hint) {
+                          const uint64_t* budget, uint64_t base_hint) {
     constexpr uint64_t MAXB = 1ull << 48;
     if (!out || !sizes) return AGILE_EINVAL;
     for (int k = 0; k < 3; ++k)
-        if (sizes[k] == 0 || sizes[k] > MAXB || (backed && backed[k] > sizes[k]))
-            return AGILE_EINVAL;
+        if (sizes[k] == 0 || sizes[k] > MAXB) return AGILE_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess) return AGILE_EDEVICE;
     if (device < 0 || device >= ndev) return AGILE_EINVAL;
@@ -200,6 +225,8 @@ int agile_aperture_create(agile_aperture** out, int device, const uint64_t* size
     if (!ap) return AGILE_ENOMEM;
     ap->device = device;
     ap->gran = g;
+    ap->prop = prop;
+    for (int k = 0; k < 3; ++k) ap->budget[k] = budget ? budget[k] : ~0ull;
     // Placement: at the caller's base if the runtime grants it; otherwise one reservation of
     // the whole layout shows where it fits, is released, and the three apertures are reserved
     // back to back at that address.
@@ -219,37 +246,6 @@ int agile_aperture_create(agile_aperture** out, int device, const uint64_t* size
         delete ap;
         return AGILE_ENOMEM;
     }
-    // Backing: one physical allocation mapped at the start of each aperture (the runtime grants
-    // access reliably to one mapping per reservation only).
-    hipMemAccessDesc acc = {};
-    acc.location = prop.location;
-    acc.flags = hipMemAccessFlagsProtReadWrite;
-    for (int k = 0; k < 3; ++k) {
-        const uint64_t n = backed ? up(backed[k]) : 0;
-        ap->va[k].reset(ap->b[k], ap->b[k] + n);
-        if (n == 0) continue;
-        void* p = reinterpret_cast<void*>(ap->b[k]);
-        if (hipMemCreate(&ap->h[k], n, &prop, 0) != hipSuccess) {
-            (void)hipGetLastError();
-            teardown(ap);
-            delete ap;
-            return AGILE_ENOMEM;
-        }
-        if (hipMemMap(p, n, 0, ap->h[k], 0) != hipSuccess) {
-            (void)hipMemRelease(ap->h[k]);
-            (void)hipGetLastError();
-            teardown(ap);
-            delete ap;
-            return AGILE_EDEVICE;
-        }
-        ap->backed[k] = n;
-        if (hipMemSetAccess(p, n, &acc, 1) != hipSuccess) {
-            (void)hipGetLastError();
-            teardown(ap);
-            delete ap;
-            return AGILE_EDEVICE;
-        }
-    }
     *out = ap;
     return AGILE_OK;
 }
@@ -260,8 +256,11 @@ int agile_aperture_destroy(agile_aperture* ap) {
     {
         DeviceGuard dg(ap->device);
         if (!dg.ok || hipDeviceSynchronize() != hipSuccess) rc = AGILE_EDEVICE;
-        for (auto& [addr, a] : ap->allocs)
+        for (auto& [addr, a] : ap->allocs) {
             if (a.rt) (void)agile_rt_remove(a.rt, a.id);
+            if (!unmap_alloc(a, addr)) rc = AGILE_EDEVICE;
+            if (!release(addr, addr + a.bytes) && !ap->user_hint) rc = AGILE_EDEVICE;
+        }
         ap->allocs.clear();
         if (!teardown(ap)) rc = AGILE_EDEVICE;
     }
@@ -269,13 +268,13 @@ int agile_aperture_destroy(agile_aperture* ap) {
     return rc;
 }
 
-int agile_aperture_info(const agile_aperture* ap, uint64_t* bounds, uint64_t* backed,
+int agile_aperture_info(const agile_aperture* ap, uint64_t* bounds, uint64_t* mapped,
                         uint64_t* granularity) {
     if (!ap) return AGILE_EINVAL;
     if (bounds)
         for (int k = 0; k < 4; ++k) bounds[k] = ap->b[k];
-    if (backed)
-        for (int k = 0; k < 3; ++k) backed[k] = ap->backed[k];
+    if (mapped)
+        for (int k = 0; k < 3; ++k) mapped[k] = ap->mapped[k];
     if (granularity) *granularity = ap->gran;
     return AGILE_OK;
 }
@@ -285,21 +284,68 @@ int agile_aperture_alloc(agile_aperture* ap, int region, uint64_t bytes, agile_r
     if (!ap || !out_ptr || region < AGILE_AP_IO || region > AGILE_AP_USER || bytes == 0 ||
         bytes > ap->b[region + 1] - ap->b[region])
         return AGILE_EINVAL;
+    if (ap->broken) return AGILE_EDEVICE;
     const uint64_t n = (bytes + ap->gran - 1) / ap->gran * ap->gran;
+    if (n > ap->budget[region] - ap->mapped[region]) return AGILE_ENOSPC;
+    uint64_t s = 0, e = 0;
+    if (!ap->va[region].first_fit(n, &s, &e)) return AGILE_ENOSPC;
+    DeviceGuard dg(ap->device);
+    if (!dg.ok) return AGILE_EDEVICE;
+    // the free run [s, e) becomes the allocation's reservation [s, s + n) and the rest
+    if (!split_run(ap, s, s + n, e)) return AGILE_EDEVICE;
     uint64_t addr = 0;
-    if (!ap->va[region].take(n, &addr)) return AGILE_ENOSPC;
-    int32_t id = -1;
+    (void)ap->va[region].take(n, &addr);  // == s: the same lowest fit
+    auto undo_va = [&]() {  // merge [s, s + n) back into the free run
+        uint64_t ms, me;
+        ap->va[region].merged(s, n, &ms, &me);
+        bool ok = release(s, s + n);
+        if (me > s + n) ok &= release(s + n, me);
+        if (ok && !reserve_exact(ms, me, ap->gran)) ap->broken = true;
+        ap->va[region].give(s, n);
+    };
+    // physical memory for this allocation alone, mapped in its own reservation, read/write
+    agile_aperture::Alloc a{n, region, rt, -1, {}};
+    if (hipMemCreate(&a.h, n, &ap->prop, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        undo_va();
+        return AGILE_ENOMEM;
+    }
+    void* p = reinterpret_cast<void*>(addr);
+    if (hipMemMap(p, n, 0, a.h, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipMemRelease(a.h);
+        undo_va();
+        return AGILE_EDEVICE;
+    }
+    hipMemAccessDesc acc = {};
+    acc.location = ap->prop.location;
+    acc.flags = hipMemAccessFlagsProtReadWrite;
+    unsigned long long f0 = 0, f1 = 0;
+    const bool granted =
+        hipMemSetAccess(p, n, &acc, 1) == hipSuccess &&
+        hipMemGetAccess(&f0, &acc.location, p) == hipSuccess &&
+        hipMemGetAccess(&f1, &acc.location, reinterpret_cast<void*>(addr + n - ap->gran)) ==
+            hipSuccess &&
+        f0 == hipMemAccessFlagsProtReadWrite && f1 == hipMemAccessFlagsProtReadWrite;
+    if (!granted) {  // never hand out memory the device may not touch
+        (void)hipGetLastError();
+        (void)unmap_alloc(a, addr);
+        undo_va();
+        return AGILE_EDEVICE;
+    }
     if (rt) {
-        // carved from the aperture's mapped backing: memory a kernel may touch
-        const int rc = agile_rt_insert(rt, addr, bytes, kind_of(region) | AGILE_RANGE_BACKED, &id);
+        // its own mapped memory: a kernel may touch it
+        const int rc = agile_rt_insert(rt, addr, bytes, kind_of(region) | AGILE_RANGE_BACKED, &a.id);
         if (rc != AGILE_OK) {
-            ap->va[region].give(addr, n);
+            (void)unmap_alloc(a, addr);
+            undo_va();
             return rc;
         }
     }
-    ap->allocs.emplace(addr, agile_aperture::Alloc{n, region, rt, id});
-    *out_ptr = reinterpret_cast<void*>(addr);
-    if (out_id) *out_id = id;
+    ap->mapped[region] += n;
+    ap->allocs.emplace(addr, a);
+    *out_ptr = p;
+    if (out_id) *out_id = a.id;
     return AGILE_OK;
 }
 
@@ -310,9 +356,23 @@ int agile_aperture_free(agile_aperture* ap, void* ptr) {
     DeviceGuard dg(ap->device);
     // wait first: on a failure nothing has changed
     if (!dg.ok || hipDeviceSynchronize() != hipSuccess) return AGILE_EDEVICE;
-    if (it->second.rt) (void)agile_rt_remove(it->second.rt, it->second.id);
-    ap->va[it->second.region].give(it->first, it->second.bytes);
+    const agile_aperture::Alloc a = it->second;
+    const uint64_t s = it->first;
+    if (!unmap_alloc(a, s)) return AGILE_EDEVICE;
+    if (a.rt) (void)agile_rt_remove(a.rt, a.id);
+    ap->mapped[a.region] -= a.bytes;
     ap->allocs.erase(it);
+    // the allocation's reservation and its free neighbours become one free run
+    uint64_t ms, me;
+    ap->va[a.region].merged(s, a.bytes, &ms, &me);
+    bool ok = release(s, s + a.bytes);
+    if (ms < s) ok &= release(ms, s);
+    if (me > s + a.bytes) ok &= release(s + a.bytes, me);
+    ap->va[a.region].give(s, a.bytes);
+    if (!ok || !reserve_exact(ms, me, ap->gran)) {
+        ap->broken = true;
+        return AGILE_EDEVICE;
+    }
     return AGILE_OK;
 }
 

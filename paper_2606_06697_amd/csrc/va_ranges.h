@@ -52,6 +52,30 @@ struct VaRanges {
         free_[s] = e;
     }
 
+    // The free run that take(n) would split: [*s, *e); false when nothing fits.
+    bool first_fit(uint64_t n, uint64_t* s, uint64_t* e) const {
+        if (n == 0) return false;
+        for (const auto& [fs, fe] : free_)
+            if (fe - fs >= n) {
+                *s = fs;
+                *e = fe;
+                return true;
+            }
+        return false;
+    }
+
+    // The free run that give(s, n) would form, merged with its free neighbours: [*ms, *me).
+    void merged(uint64_t s, uint64_t n, uint64_t* ms, uint64_t* me) const {
+        *ms = s;
+        *me = s + n;
+        auto nx = free_.lower_bound(s);
+        if (nx != free_.end() && nx->first == s + n) *me = nx->second;
+        if (nx != free_.begin()) {
+            auto pv = std::prev(nx);
+            if (pv->second == s) *ms = pv->first;
+        }
+    }
+
     bool whole() const { return free_.size() == 1 && free_.begin()->first == lo && free_.begin()->second == hi; }
 };
 

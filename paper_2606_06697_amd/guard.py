@@ -485,10 +485,10 @@ class RangeTable:
 
 
 # ---- fixed address apertures (include/agile_aperture.h) -----------------------------------
-def agile_aperture_create(device: int, sizes, backed=None, base_hint: int = 0) -> int:
-    """sizes / backed: three byte counts (I/O, module, user)."""
+def agile_aperture_create(device: int, sizes, budget=None, base_hint: int = 0) -> int:
+    """sizes / budget: three byte counts (I/O, module, user); budget None: no limit."""
     sz = (ctypes.c_uint64 * 3)(*[int(x) for x in sizes])
-    bk = (ctypes.c_uint64 * 3)(*[int(x) for x in backed]) if backed is not None else None
+    bk = (ctypes.c_uint64 * 3)(*[int(x) for x in budget]) if budget is not None else None
     h = _vp()
     _check(lib().agile_aperture_create(ctypes.byref(h), device, ctypes.cast(sz, _vp),
                                        ctypes.cast(bk, _vp) if bk is not None else None,
@@ -501,7 +501,7 @@ def agile_aperture_destroy(ap: int) -> None:
 
 
 def agile_aperture_info(ap: int):
-    """Returns ((io start, module start, user start, user end), backed bytes per aperture,
+    """Returns ((io start, module start, user start, user end), mapped bytes per aperture,
     granularity)."""
     b = (ctypes.c_uint64 * 4)()
     k = (ctypes.c_uint64 * 3)()

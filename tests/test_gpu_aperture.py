@@ -6,8 +6,9 @@
 * the coarse check ``agile_validate_aperture`` against the oracle, bit-exact, on every
   boundary address with lengths that reach every boundary, random and extreme queries, ragged
   sizes (bytes past n untouched) and without the index output;
-* allocations: carved at the lowest free address of their aperture's backing, registered in a
-  range table with the kind of their aperture, readable and writable by the guarded kernels
+* allocations: each with physical memory of its own, mapped at the lowest free address of its
+  aperture in a reservation of its own, registered in a range table with the kind of their
+  aperture, readable and writable by the guarded kernels
   (parity with the oracle, fault log included); table validation agrees with the apertures (a table
   ALLOW is an aperture ALLOW, a table PROTECTED an aperture PROTECTED); a freed allocation is
   UNMAPPED in the table but still ALLOW for the apertures, and its addresses are reused.
@@ -97,8 +98,8 @@ def test_layout_and_validation_parity():
     g = guard_mod()
     ap = g.agile_aperture_create(0, (64 * MiB + 5, 256 * MiB, 4 * GiB))
     try:
-        bounds, backed, gran = g.agile_aperture_info(ap)
-        assert backed == (0, 0, 0)
+        bounds, mapped, gran = g.agile_aperture_info(ap)
+        assert mapped == (0, 0, 0)
         assert gran > 0 and gran & (gran - 1) == 0
         assert bounds[0] % gran == 0
         assert bounds[1] - bounds[0] == up(64 * MiB + 5, gran)
@@ -157,8 +158,8 @@ def test_allocations_are_registered_and_guarded():
     tw = Twin(64)
     ap = g.agile_aperture_create(0, (16 * MiB, 64 * MiB, 1 * GiB), (4 * MiB, MiB, 256 * MiB))
     try:
-        bounds, backed, gran = g.agile_aperture_info(ap)
-        assert backed == (up(4 * MiB, gran), up(MiB, gran), up(256 * MiB, gran))
+        bounds, mapped, gran = g.agile_aperture_info(ap)
+        assert mapped == (0, 0, 0)
         rng = np.random.default_rng(9)
         # (name, aperture, requested bytes, oracle kind)
         plan = [("A", g.AP_USER, MiB + 3, USER), ("B", g.AP_USER, 5 * MiB, USER),
@@ -174,6 +175,10 @@ def test_allocations_are_registered_and_guarded():
         assert addr["X"] == addr["B"] + up(5 * MiB, gran)
         assert addr["M"] == bounds[1] and addr["I"] == bounds[0]
         assert len(tw.rt) == 5
+        # each allocation maps its request rounded up to the granularity
+        _, mapped, _ = g.agile_aperture_info(ap)
+        assert mapped == (up(4096, gran), up(64 << 10, gran),
+                          up(MiB + 3, gran) + up(5 * MiB, gran) + up(8 * 4096, gran))
 
         # fill A, B, X and M with known bytes (unguarded copies from torch memory)
         mem = Memory()
@@ -256,7 +261,7 @@ def test_allocations_are_registered_and_guarded():
         assert e.value.code == g.AGILE_EINVAL          # larger than the aperture
         with pytest.raises(g.AgileError) as e:
             g.agile_aperture_alloc(ap, g.AP_IO, 8 * MiB, tw.h)
-        assert e.value.code == g.AGILE_ENOSPC          # fits the aperture, not its backing
+        assert e.value.code == g.AGILE_ENOSPC          # fits the aperture, not its budget
     finally:
         g.agile_aperture_destroy(ap)
     assert len(tw.rt) == 0       # destroy removed what was still registered
@@ -298,3 +303,78 @@ def test_full_size_sampled():
         del q, v, r
     finally:
         g.agile_aperture_destroy(ap)
+
+
+def test_each_allocation_maps_its_own_memory():
+    """Section V-A: memory is created, mapped and made accessible per allocation. Thirty
+    allocations of mixed sizes (3 B to 96 MiB, ragged; the patterns that lose device access when
+    mapped side by side in one large reservation among them) in the user and module apertures
+    of Table I's sizes, packed at the granularity, then freed and made again in the holes; every
+    live allocation holds its own bytes (a distinct pattern written through it reads back from
+    it alone), mapped bytes are accounted per aperture, and the table follows every step."""
+    need_gpu()
+    g = guard_mod()
+    tw = Twin(256)
+    ap = g.agile_aperture_create(0, (64 << 30, 448 << 30, 1 << 40))
+    try:
+        bounds, _, gran = g.agile_aperture_info(ap)
+        rng = np.random.default_rng(17)
+        live = {}   # address -> (region, bytes, pattern seed)
+
+        def alloc(region, nb):
+            p, rid = g.agile_aperture_alloc(ap, region, nb, tw.h)
+            assert rid == tw.ot.insert(p, nb, USER if region == g.AP_USER else PROTECTED)
+            assert p % gran == 0 and bounds[region] <= p and p + nb <= bounds[region + 1]
+            seed = int(rng.integers(1 << 30))
+            data = np.random.default_rng(seed).integers(0, 256, nb, dtype=np.uint8)
+            g.agile_unguarded_copy(p, torch.from_numpy(data).cuda(), nb)
+            live[p] = (region, nb, seed, rid)
+            return p
+
+        def check_all():
+            torch.cuda.synchronize()
+            for p, (region, nb, seed, _) in live.items():
+                out = torch.empty(nb, dtype=torch.uint8, device="cuda")
+                g.agile_unguarded_copy(out, p, nb)
+                want = np.random.default_rng(seed).integers(0, 256, nb, dtype=np.uint8)
+                assert np.array_equal(out.cpu().numpy(), want), hex(p)
+            _, mapped, _ = g.agile_aperture_info(ap)
+            for k in range(3):
+                assert mapped[k] == sum(up(nb, gran) for r, nb, _, _ in live.values() if r == k)
+            assert len(tw.rt) == len(live)
+
+        sizes = [4096, MiB + 13, 3, 256 << 10, 96 * MiB + 5, 2 * MiB, 2 * MiB + 1, 64 << 10,
+                 5000, 17 * MiB, 12 << 10, 4 * MiB - 1]
+        order = []
+        for k in range(24):
+            region = g.AP_USER if k % 4 else g.AP_MODULE
+            order.append(alloc(region, sizes[k % len(sizes)]))
+        check_all()
+        # free every third allocation, then allocate again: the holes are reused lowest-fit
+        for p in order[::3]:
+            g.agile_aperture_free(ap, p)
+            tw.ot.remove(live.pop(p)[3])
+        check_all()
+        again = []
+        for k in range(6):
+            region = g.AP_USER if k % 2 else g.AP_MODULE
+            again.append(alloc(region, sizes[(k * 5) % len(sizes)]))
+        freed = sorted(order[::3])
+        assert min(again) <= max(freed)          # some hole was reused
+        check_all()
+        # table validation of the live allocations: ALLOW inside, PROTECTED in the module
+        # aperture's ones, UNMAPPED in the freed units no allocation took back
+        qa = np.array([p for p in live] + [p + nb - 1 for p, (_, nb, _, _) in live.items()],
+                      dtype=np.uint64)
+        ql = np.ones(qa.size, dtype=np.uint64)
+        q = qtensor(qa, ql)
+        tv = torch.empty(qa.size, dtype=torch.uint8, device="cuda")
+        to = torch.empty(qa.size, dtype=torch.int32, device="cuda")
+        g.agile_validate_ptrs(tw.h, q, qa.size, tv, to)
+        torch.cuda.synchronize()
+        ev, eo = tw.ot.verdict_many(qa, ql)
+        assert np.array_equal(tv.cpu().numpy(), ev) and np.array_equal(to.cpu().numpy(), eo)
+    finally:
+        g.agile_aperture_destroy(ap)
+    assert len(tw.rt) == 0
+    tw.close()

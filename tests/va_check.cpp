@@ -1,7 +1,8 @@
 // CPU check of agile::VaRanges against a granule map: random take/give sequences in granule
 // units; every take must return the lowest start of a long-enough free run (found by scanning
-// the map), stay inside the aperture and overlap nothing live; giving everything back must
-// leave one free range covering the aperture.
+// the map), stay inside the aperture and overlap nothing live, and first_fit must name the run
+// it splits; merged must name the run each give forms; giving everything back must leave one
+// free range covering the aperture.
 #include <stdio.h>
 #include <stdlib.h>
 
@@ -35,8 +36,12 @@ int main() {
                     while (k < want && !map[g + k]) ++k;
                     if (k == want) expect = (int64_t)g;
                 }
+                uint64_t fs = 0, fe = 0;
+                const bool fit = va.first_fit(want * G, &fs, &fe);
                 uint64_t addr = 0;
                 const bool ok = va.take(want * G, &addr);
+                if (fit != ok) return fail("first_fit agrees with take", step);
+                if (ok && (fs != addr || fe < addr + want * G)) return fail("first_fit run", step);
                 if (ok != (expect >= 0)) return fail("fit", step);
                 if (!ok) continue;
                 if (addr < lo || (addr - lo) % G) return fail("alignment", step);
@@ -53,7 +58,13 @@ int main() {
                 const auto [g0, cnt] = live[j];
                 live[j] = live.back();
                 live.pop_back();
+                uint64_t ms = 0, me = 0;
+                va.merged(lo + g0 * G, cnt * G, &ms, &me);
                 va.give(lo + g0 * G, cnt * G);
+                {
+                    auto it = va.free_.find(ms);
+                    if (it == va.free_.end() || it->second != me) return fail("merged run", step);
+                }
                 for (uint64_t k = 0; k < cnt; ++k) map[g0 + k] = 0;
             }
             // free ranges are maximal and match the map
