@@ -657,8 +657,10 @@ hipError_t launch_scatter_add(bool guard, const DevTable& t, DevLog* log, const 
         } else {
             const uint64_t span = (uint64_t)rg.g.rhi - (uint64_t)rg.g.rlo;
             if (span >= SRT_SENT) sorted = false;
+            // enough bits for span + 1, so that no key equals the sentinel in the sorted bits
+            // (the largest key of a 2^16-row table is all ones in 16 bits)
             uint32_t bits = 0;
-            while (bits < 32 && (span >> bits)) ++bits;
+            while (bits < 32 && ((span + 1) >> bits)) ++bits;
             npasses = (bits + 7) / 8;
             if (npasses == 0) npasses = 1;
         }

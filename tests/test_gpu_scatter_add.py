@@ -6,7 +6,8 @@ destination values are small integers, so every sum is exact in any order and th
 equal the oracle's memory byte for byte. Cases: hot and hostile indices (protected, hole,
 other allocation, negative, huge), an index buffer and a source buffer that run out before n, an
 interior destination pointer (negative indices allowed), a destination with no binding (no row
-takes the sorted path), and the unguarded twin on valid indices.
+takes the sorted path), destinations of exactly 2^8 and 2^16 rows (the last row's key has every
+sorted bit set, as the hostile rows' key has), and the unguarded twin on valid indices.
 """
 import random
 
@@ -23,11 +24,11 @@ NMAX = 70001
 CASES = [(4, 1), (4, 3), (4, 64), (4, 128), (8, 2), (8, 32)]
 
 
-def layout(w, D):
+def layout(w, D, rows=DST_ROWS):
     rb = w * D
     off = {}
     o = 0
-    for name, size in (("dst", DST_ROWS * rb), ("prot", 4096), ("hole", 4096), ("other", 8192),
+    for name, size in (("dst", rows * rb), ("prot", 4096), ("hole", 4096), ("other", 8192),
                        ("idx", NMAX * 8), ("src", NMAX * rb)):
         o = (o + 255) // 256 * 256
         off[name] = (o, o + size)
@@ -35,9 +36,9 @@ def layout(w, D):
     return off, (o + 4095) // 4096 * 4096
 
 
-def setup(w, D, seed):
+def setup(w, D, seed, rows=DST_ROWS):
     need_gpu()
-    off, size = layout(w, D)
+    off, size = layout(w, D, rows)
     ar = Arena(size, seed)
     tw = Twin(16)
     kinds = {"dst": 0, "prot": 1, "other": 0, "idx": 0, "src": 0}
@@ -99,6 +100,33 @@ def test_sorted_scatter_add_against_oracle(w, D):
         G.scatter_vec(tw.ot, ar.mem, ol, tw.next_seq(), tr["dst"], rb, idx_ptr, src, n, w, True)
         ar.check(f"scatter-add w={w} D={D} trial {t} n={n}")
         log_matches(tw, ol, f"scatter-add w={w} D={D} trial {t}")
+    tw.close()
+
+
+@pytest.mark.parametrize("w,D,rows", [(4, 4, 256), (4, 1, 65536), (8, 1, 256)])
+def test_sorted_scatter_add_last_row_of_a_power_of_two_table(w, D, rows):
+    """Rows that fail the guard's fast test sort after every allowed row, also when the table has
+    exactly 2^8 or 2^16 rows and its last row's key is all ones in the sorted bits: every update
+    of the last row lands, hostile rows are dropped and logged, as in the oracle."""
+    ar, tw, off = setup(w, D, 300 + rows + w, rows=rows)
+    rb = w * D
+    dtype = 0 if w == 4 else 1
+    rng = np.random.default_rng(rows + w)
+    n = 40000
+    u = rng.random(n)
+    idx = rng.integers(0, rows, n)
+    idx[u < 0.3] = rows - 1
+    bad = np.array([rows, rows + 5, -1, 1 << 40], dtype=np.int64)
+    idx[u > 0.9] = bad[rng.integers(0, bad.size, int((u > 0.9).sum()))]
+    ar.write(off["idx"][0], idx.astype(np.int64))
+    base = ar.addr(off["dst"][0])
+    ol = G.FaultLog()
+    tw.g.agile_guarded_scatter(tw.h, base, rb, ar.addr(off["idx"][0]), ar.addr(off["src"][0]), n,
+                               dtype, 1)
+    G.scatter_vec(tw.ot, ar.mem, ol, tw.next_seq(), base, rb, ar.addr(off["idx"][0]),
+                  ar.addr(off["src"][0]), n, w, True)
+    ar.check(f"scatter-add into {rows} rows")
+    log_matches(tw, ol, f"scatter-add into {rows} rows")
     tw.close()
 
 
