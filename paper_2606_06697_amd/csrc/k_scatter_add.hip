@@ -6,9 +6,10 @@
 // wholly inside its allowed prefix, destination row inside the binding's row interval) get a
 // 32-bit key, their destination row's offset inside that interval; every other row gets the
 // largest key. A stable LSD radix sort (8-bit digits; per pass: per-tile digit histograms, their
-// exclusive scan, a stable scatter ranked with wave ballots; a pass whose digit is the same for
-// every key is skipped on the device) orders (key, position) pairs by destination row,
-// position ascending. Each wave then walks a tile of 256 sorted entries and sums the source rows
+// exclusive scan, a stable scatter that ranks a tile's keys with wave ballots and regroups them
+// by digit in LDS, so that each digit's keys leave the tile as one contiguous run; a pass whose
+// digit is the same for every key is skipped on the device) orders (key, position) pairs by
+// destination row, position ascending. Each wave then walks a tile of 256 sorted entries and sums the source rows
 // of each run of equal keys in position order; a run that lies wholly inside the tile owns its
 // destination row and adds with a plain read-modify-write, a run that crosses a tile boundary
 // adds with one atomic per element. Rows that failed the fast test follow in a separate kernel
@@ -205,11 +206,11 @@ __global__ __launch_bounds__(SABLOCK) void k_scatter_add(DevTable t, DevLog* log
 // ================================================================ sorted path
 constexpr int SRT_BLOCK = 256;
 constexpr uint32_t SRT_TILE = 4096;   // keys per histogram / scatter tile (16 per thread)
-constexpr uint32_t SRT_KPT = SRT_TILE / SRT_BLOCK;
+constexpr uint32_t SRT_TB = 1024;      // threads of the histogram and scatter workgroups
 constexpr uint32_t SRT_SENT = 0xFFFFFFFFu;
 constexpr uint32_t RED_TILE = 256;    // sorted entries per reduce wave
-// ctl[p] (p < 4): pass p was skipped (one digit value only); ctl[4 + p]: buffer pass p reads,
-// ctl[8 + p]: the buffer the reduce reads when the sort has p passes
+// ctl[p] (p < 4): pass p was skipped (one digit value only); ctl[4 + p]: the buffer pass p reads
+// (ctl[4 + npasses]: the buffer holding the sorted result, which the reduce reads)
 constexpr int CTL_WORDS = 16;
 
 struct SortBufs {
@@ -217,7 +218,7 @@ struct SortBufs {
     uint32_t* vals[2];
     uint32_t* hist;  // [256 * ntiles], scanned in place
     uint32_t* ctl;   // [CTL_WORDS]
-    uint32_t* dstart;  // [256]: digit totals, then the first output position of each digit
+    uint32_t* dstart;  // [256]: the current pass's digit totals
     uint64_t* slow;  // [ceil(n / 64)]: bit l of word w marks row 64 w + l as failing the fast test
 };
 
@@ -275,27 +276,31 @@ __global__ __launch_bounds__(SRT_BLOCK) void k_srt_keys(const int64_t* __restric
     }
 }
 
-__global__ __launch_bounds__(SRT_BLOCK) void k_srt_hist(SortBufs b, uint64_t n, uint32_t pass) {
+__global__ __launch_bounds__(SRT_TB) void k_srt_hist(SortBufs b, uint64_t n, uint32_t pass) {
     __shared__ uint32_t h[256];
     const uint32_t tid = threadIdx.x, shift = 8 * pass;
     const uint32_t* keys = b.keys[b.ctl[4 + pass]];
-    h[tid] = 0;
+    if (tid < 256) h[tid] = 0;
     __syncthreads();
     const uint64_t t0 = (uint64_t)blockIdx.x * SRT_TILE;
-#pragma unroll 4
-    for (uint32_t k = 0; k < SRT_KPT; ++k) {
-        const uint64_t i = t0 + k * SRT_BLOCK + tid;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    uint32_t k[SRT_TILE / SRT_TB];
+#pragma unroll
+    for (uint32_t r = 0; r < SRT_TILE / SRT_TB; ++r) {
+        const uint64_t i = t0 + r * SRT_TB + tid;
+        k[r] = i < n ? keys[i] : 0u;
     }
+#pragma unroll
+    for (uint32_t r = 0; r < SRT_TILE / SRT_TB; ++r)
+        if (t0 + r * SRT_TB + tid < n) atomicAdd(&h[(k[r] >> shift) & 255u], 1u);
     __syncthreads();
-    b.hist[(uint64_t)tid * gridDim.x + blockIdx.x] = h[tid];
+    if (tid < 256) b.hist[(uint64_t)tid * gridDim.x + blockIdx.x] = h[tid];
 }
 
-// Offsets of a pass in two small steps. k_srt_scan_rows: one workgroup per digit turns the
-// digit's per-tile counts into exclusive prefixes and records the digit's total.
-// k_srt_scan_digits: one workgroup turns the 256 totals into each digit's first output position,
-// sets the pass's skip flag (one digit holds all n keys) and the buffer the next pass reads.
-__device__ inline uint32_t block_scan256(uint32_t v, uint32_t* wsum, uint32_t& total) {
+// Offsets of a pass. k_srt_scan_rows: one workgroup per digit turns the digit's per-tile counts
+// into exclusive prefixes and records the digit's total; the scatter's workgroups then turn the
+// 256 totals into each digit's first output position themselves.
+template <uint32_t NT>
+__device__ inline uint32_t block_scan(uint32_t v, uint32_t* wsum, uint32_t& total) {
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
     uint32_t inc = v;
     for (int o = 1; o < 64; o <<= 1) {
@@ -306,7 +311,7 @@ __device__ inline uint32_t block_scan256(uint32_t v, uint32_t* wsum, uint32_t& t
     __syncthreads();
     uint32_t before = 0;
     total = 0;
-    for (uint32_t k = 0; k < SRT_BLOCK / 64; ++k) {
+    for (uint32_t k = 0; k < NT / 64; ++k) {
         if (k < wv) before += wsum[k];
         total += wsum[k];
     }
@@ -322,56 +327,67 @@ __global__ __launch_bounds__(SRT_BLOCK) void k_srt_scan_rows(SortBufs b, uint32_
         const uint32_t t = t0 + threadIdx.x;
         const uint32_t v = t < ntiles ? row[t] : 0u;
         uint32_t total;
-        const uint32_t ex = block_scan256(v, wsum, total);
+        const uint32_t ex = block_scan<SRT_BLOCK>(v, wsum, total);
         if (t < ntiles) row[t] = carry + ex;
         carry += total;
     }
     if (threadIdx.x == 0) b.dstart[blockIdx.x] = carry;
 }
 
-__global__ __launch_bounds__(SRT_BLOCK) void k_srt_scan_digits(SortBufs b, uint64_t n, uint32_t pass) {
-    __shared__ uint32_t wsum[SRT_BLOCK / 64];
+// Stable scatter of one pass over a tile of SRT_TILE keys. The workgroup first turns the 256 digit
+// totals into each digit's first output position (a pass whose digit is the same for all n keys is
+// skipped; workgroup 0 records that, and which buffer the next pass reads). Each wave then ranks
+// its SRT_TILE / 16 consecutive keys by digit in rounds of 64: wave ballots rank equal digits by
+// lane, and a per-wave running count per digit carries the order from round to round (a wave's
+// LDS reads and writes take effect in program order, so no barrier is needed between rounds).
+// The tile's keys are regrouped by digit in LDS, in position order within a digit, and each
+// digit's group is written to its place in the output as one contiguous run.
+__global__ __launch_bounds__(SRT_TB) void k_srt_scatter(SortBufs b, uint64_t n, uint32_t pass) {
+    constexpr uint32_t NW = SRT_TB / 64;
+    constexpr uint32_t R = SRT_TILE / SRT_TB;  // rounds per wave
+    __shared__ uint32_t wc[NW][256];  // keys per wave and digit, then each wave's offset in the digit
+    __shared__ uint32_t lstart[256];  // first slot of each digit in the regrouped tile
+    __shared__ uint32_t gstart[256];  // output position of the tile's first key of each digit
+    __shared__ uint32_t sk[SRT_TILE], sv[SRT_TILE];
+    __shared__ uint32_t wsum[NW];
     __shared__ uint32_t skip;
-    const uint32_t tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6, shift = 8 * pass;
+    const uint32_t src = b.ctl[4 + pass];
     if (tid == 0) skip = 0;
-    const uint32_t tot = b.dstart[tid];
+    const uint32_t tot = tid < 256 ? b.dstart[tid] : 0u;
     __syncthreads();
-    if ((uint64_t)tot == n) skip = 1;
+    if (tid < 256 && (uint64_t)tot == n) skip = 1;
     uint32_t all;
-    const uint32_t ex = block_scan256(tot, wsum, all);
-    b.dstart[tid] = ex;
-    if (tid == 0) {
-        const uint32_t src = b.ctl[4 + pass];
+    const uint32_t dfirst = block_scan<SRT_TB>(tot, wsum, all);
+    if (blockIdx.x == 0 && tid == 0) {
         b.ctl[pass] = skip;
         b.ctl[4 + pass + 1] = skip ? src : 1u - src;
     }
-}
-
-// Stable scatter of one pass: items are taken in rounds of 256 consecutive positions; inside a
-// round, wave ballots rank equal digits by lane, per-wave digit counts rank them across waves, and
-// a running per-digit count carries the order from round to round.
-__global__ __launch_bounds__(SRT_BLOCK) void k_srt_scatter(SortBufs b, uint64_t n, uint32_t pass) {
-    if (b.ctl[pass]) return;
-    __shared__ uint32_t run[256];
-    __shared__ uint32_t wcnt[SRT_BLOCK / 64][256];
-    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6, shift = 8 * pass;
-    const uint32_t src = b.ctl[4 + pass];
+    if (skip) return;
     const uint32_t* kin = b.keys[src];
     const uint32_t* vin = b.vals[src];
     uint32_t* kout = b.keys[1u - src];
     uint32_t* vout = b.vals[1u - src];
-    run[tid] = b.dstart[tid] + b.hist[(uint64_t)tid * gridDim.x + blockIdx.x];
-    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
-    const uint64_t t0 = (uint64_t)blockIdx.x * SRT_TILE;
-    for (uint32_t k = 0; k < SRT_KPT; ++k) {
+    if (tid < 256) {
 #pragma unroll
-        for (int w = 0; w < SRT_BLOCK / 64; ++w) wcnt[w][tid] = 0;
-        __syncthreads();
-        const uint64_t i = t0 + k * SRT_BLOCK + tid;
-        const bool valid = i < n;
-        const uint32_t key = valid ? kin[i] : 0u;
-        const uint32_t val = valid ? vin[i] : 0u;
-        const uint32_t d = (key >> shift) & 255u;
+        for (uint32_t w = 0; w < NW; ++w) wc[w][tid] = 0;
+        gstart[tid] = dfirst + b.hist[(uint64_t)tid * gridDim.x + blockIdx.x];
+    }
+    __syncthreads();
+    const uint64_t t0 = (uint64_t)blockIdx.x * SRT_TILE;
+    const uint64_t w0 = t0 + (uint64_t)wv * (SRT_TILE / NW);
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    uint32_t key[R], val[R], pre[R];
+#pragma unroll
+    for (uint32_t r = 0; r < R; ++r) {
+        const uint64_t i = w0 + r * 64 + lane;
+        key[r] = i < n ? kin[i] : 0u;
+        val[r] = i < n ? vin[i] : 0u;
+    }
+#pragma unroll
+    for (uint32_t r = 0; r < R; ++r) {
+        const bool valid = w0 + r * 64 + lane < n;
+        const uint32_t d = (key[r] >> shift) & 255u;
         uint64_t match = __ballot(valid);
 #pragma unroll
         for (int bit = 0; bit < 8; ++bit) {
@@ -379,20 +395,40 @@ __global__ __launch_bounds__(SRT_BLOCK) void k_srt_scatter(SortBufs b, uint64_t 
             match &= ((d >> bit) & 1u) ? bb : ~bb;
         }
         const uint32_t rank = (uint32_t)__popcll(match & below);
-        if (valid && rank == 0) wcnt[wv][d] = (uint32_t)__popcll(match);
-        __syncthreads();
-        if (valid) {
-            uint32_t pos = run[d] + rank;
-            for (uint32_t w = 0; w < wv; ++w) pos += wcnt[w][d];
-            kout[pos] = key;
-            vout[pos] = val;
-        }
-        __syncthreads();
-        uint32_t add = 0;
+        pre[r] = wc[wv][d] + rank;
+        if (valid && rank == 0) wc[wv][d] = pre[r] + (uint32_t)__popcll(match);
+    }
+    __syncthreads();
+    // thread tid < 256 owns digit tid: the tile's count, and each wave's offset inside the digit
+    uint32_t cnt = 0;
+    if (tid < 256) {
 #pragma unroll
-        for (int w = 0; w < SRT_BLOCK / 64; ++w) add += wcnt[w][tid];
-        run[tid] += add;
-        __syncthreads();
+        for (uint32_t w = 0; w < NW; ++w) {
+            const uint32_t c = wc[w][tid];
+            wc[w][tid] = cnt;
+            cnt += c;
+        }
+    }
+    const uint32_t lfirst = block_scan<SRT_TB>(cnt, wsum, all);
+    if (tid < 256) lstart[tid] = lfirst;
+    __syncthreads();
+#pragma unroll
+    for (uint32_t r = 0; r < R; ++r) {
+        if (w0 + r * 64 + lane < n) {
+            const uint32_t d = (key[r] >> shift) & 255u;
+            const uint32_t slot = lstart[d] + wc[wv][d] + pre[r];
+            sk[slot] = key[r];
+            sv[slot] = val[r];
+        }
+    }
+    __syncthreads();
+    const uint32_t m = (uint32_t)(n - t0 < SRT_TILE ? n - t0 : SRT_TILE);
+    for (uint32_t q = tid; q < m; q += SRT_TB) {
+        const uint32_t k = sk[q];
+        const uint32_t d = (k >> shift) & 255u;
+        const uint32_t pos = gstart[d] + (q - lstart[d]);
+        kout[pos] = k;
+        vout[pos] = sv[q];
     }
 }
 
@@ -599,10 +635,9 @@ static void scatter_add_sorted(const DevTable& t, DevLog* log, void* dst, uint64
     const uint32_t kgrid = (uint32_t)(kg < (uint64_t)d.num_cu * 8 ? kg : (uint64_t)d.num_cu * 8);
     hipLaunchKernelGGL((k_srt_keys<G>), dim3(kgrid), dim3(SRT_BLOCK), 0, s, idx, n, rg, b);
     for (uint32_t p = 0; p < npasses; ++p) {
-        hipLaunchKernelGGL(k_srt_hist, dim3(ntiles), dim3(SRT_BLOCK), 0, s, b, n, p);
+        hipLaunchKernelGGL(k_srt_hist, dim3(ntiles), dim3(SRT_TB), 0, s, b, n, p);
         hipLaunchKernelGGL(k_srt_scan_rows, dim3(256), dim3(SRT_BLOCK), 0, s, b, ntiles);
-        hipLaunchKernelGGL(k_srt_scan_digits, dim3(1), dim3(SRT_BLOCK), 0, s, b, n, p);
-        hipLaunchKernelGGL(k_srt_scatter, dim3(ntiles), dim3(SRT_BLOCK), 0, s, b, n, p);
+        hipLaunchKernelGGL(k_srt_scatter, dim3(ntiles), dim3(SRT_TB), 0, s, b, n, p);
     }
     const uint64_t waves = (n + RED_TILE - 1) / RED_TILE;
     const uint64_t rg_blocks = (waves + 3) / 4;
