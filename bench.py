@@ -493,7 +493,8 @@ def bench_tokens(g):
 def bench_embedding(g, args):
     """Guarded embedding (1,048,576 x 256 fp32 table, 2^20 Zipf(1.1) indices, 0.01% aimed at a
     protected range right after the table): forward gather and scatter-add backward, guarded
-    and unguarded (same kernels with the guard compiled out), HIP-event medians."""
+    and unguarded (same kernels with the guard compiled out), and PyTorch's index_select /
+    index_add_ on the same work with the out-of-range indices masked, HIP-event medians."""
     import numpy as np
     import torch
     from synth import uniform_f32, zipf_indices
@@ -518,11 +519,19 @@ def bench_embedding(g, args):
     t.insert(dW.data_ptr(), R * rb, g.KIND_USER)
     ih = idx.cpu().numpy()
     distinct = int(np.unique(ih[(ih >= 0) & (ih < R)]).size)
+    # PyTorch's own ops on the same work, for context: indices outside the table masked to row 0
+    # and their gradient rows zeroed beforehand (outside the timed region)
+    bad = (idx < 0) | (idx >= R)
+    idx_m = torch.where(bad, torch.zeros_like(idx), idx)
+    dY_m = dY.view(N, D).masked_fill(bad[:, None], 0.0)
+    W2, Y2, dW2 = W.view(R, D), Y.view(N, D), torch.zeros(R, D, device=dev)
     ts = time_blocks({
         "forward": lambda: g.agile_guarded_gather(t.handle, Y, W, rb, idx, N),
         "forward_unguarded": lambda: g.agile_unguarded_gather(Y, Wbuf, rb, idx, N),
         "backward": lambda: g.agile_guarded_scatter(t.handle, dW, rb, idx, dY, N, 0, 1),
         "backward_unguarded": lambda: g.agile_unguarded_scatter(dWbuf, rb, idx, dY, N, 0, 1),
+        "torch_index_select": lambda: torch.index_select(W2, 0, idx_m, out=Y2),
+        "torch_index_add": lambda: dW2.index_add_(0, idx_m, dY_m),
     }, 2, 10)
     rc, f = t.fault_log(clear=True)
     nbad = int(((ih < 0) | (ih >= R)).sum())
@@ -546,6 +555,8 @@ def bench_embedding(g, args):
            "faults_per_call": int(f["count"]) // calls_guarded}
     out["forward_guarded_over_unguarded"] = round(med["forward_unguarded"] / med["forward"], 4)
     out["backward_guarded_over_unguarded"] = round(med["backward_unguarded"] / med["backward"], 4)
+    out["torch_index_select_over_forward_time"] = round(med["torch_index_select"] / med["forward"], 3)
+    out["torch_index_add_over_backward_time"] = round(med["torch_index_add"] / med["backward"], 3)
     return out
 
 
