@@ -193,6 +193,16 @@ def main():
     }, args.warmup, args.steps)
     dt.fault_log(clear=True)
     torch.cuda.synchronize()
+    # PyTorch's own ops on the same work, for context (no guard; out-of-range indices masked to
+    # row 0 beforehand), into separate outputs
+    a_t, out_t = torch.empty_like(a), torch.empty_like(out)
+    idx_m = torch.where((idx < 0) | (idx >= GATHER_ROWS), torch.zeros_like(idx), idx)
+    tref = time_blocks({
+        "triad_torch": lambda: torch.add(b, c, alpha=3.0, out=a_t),
+        "gather_torch": lambda: torch.index_select(table, 0, idx_m, out=out_t),
+    }, args.warmup, args.steps)
+    torch.cuda.synchronize()
+    del a_t, out_t, idx_m
     ug = {"triad": twin["triad_unguarded"], "gather": twin["gather_unguarded"]}
     ok_triad = torch.equal(a.view(torch.int32), a_ref.view(torch.int32))
     good = (idx >= 0) & (idx < GATHER_ROWS)
@@ -269,7 +279,9 @@ def main():
                       "gather_sink": round(med(pol["gather_sink"]), 4),
                       "gather_report": round(med(pol["gather_report"]), 4),
                       "gather_remap": round(med(pol["gather_remap"]), 4),
-                      "gather_unguarded": round(ug_g, 4)},
+                      "gather_unguarded": round(ug_g, 4),
+                      "triad_torch": round(med(tref["triad_torch"]), 4),
+                      "gather_torch": round(med(tref["gather_torch"]), 4)},
         "guarded_gbps": {k: round(v, 1) for k, v in gbs.items()},
         "unguarded_gbps": {k: round(v, 1) for k, v in ugbs.items()},
         "guarded_gbps_isolated": {k: round(v, 1) for k, v in gbs_twin.items()},
