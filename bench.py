@@ -232,6 +232,28 @@ def main():
     torch.cuda.synchronize()
     g.agile_aperture_destroy(ap)
     del qa
+    # PyTorch's own formulation of the same validation, for context: searchsorted over the sorted
+    # bases, then the end, kind and length tests as tensor ops; its verdicts and owners are
+    # compared with the kernel's
+    tbase, tend, tkind = tb.base.to(dev), (tb.base + tb.size).to(dev), tb.kind.to(dev)
+    qad, qln = q[:, 0].contiguous(), q[:, 1].contiguous()
+
+    def torch_validate():
+        j = torch.searchsorted(tbase, qad, right=True) - 1
+        jc = j.clamp_min(0)
+        e = tend[jc]
+        inside = (j >= 0) & (qad < e)
+        ok = qln.clamp_min(1) <= e - qad
+        v = torch.where(~inside, 3, torch.where(tkind[jc] != 0, 1, torch.where(ok, 0, 2)))
+        return v.to(torch.uint8), torch.where(inside, jc, -1).to(torch.int32)
+
+    tval = time_blocks({"validate_torch": torch_validate}, 1, max(3, args.steps // 4))
+    v_t, o_t = torch_validate()
+    g.agile_validate_ptrs(vt.handle, q, nq, verdict, owner)
+    torch.cuda.synchronize()
+    torch_equal = bool(torch.equal(v_t, verdict)) and bool(torch.equal(o_t, owner))
+    del tbase, tend, tkind, qad, qln, v_t, o_t
+    torch.cuda.empty_cache()
 
     def med(x):
         return float(np.median(np.array(x)))
@@ -273,6 +295,11 @@ def main():
                    "gather_idx": GATHER_N, "gather_rows": GATHER_ROWS},
         "validations_per_s": round(nq / (t_v / 1e3), 1),
         "dma_checks_per_s": round(nq / (med(twin["validate_dma"]) / 1e3), 1),
+        "validate_torch": {"formulation": "torch.searchsorted over the sorted bases, then the "
+                                          "end, kind and length tests as tensor ops",
+                           "kernel_ms": round(med(tval["validate_torch"]), 3),
+                           "validations_per_s": round(nq / (med(tval["validate_torch"]) / 1e3), 1),
+                           "results_equal": torch_equal},
         "kernel_ms": {"validate": round(t_v, 4), "validate_dma": round(med(twin["validate_dma"]), 4),
                       "triad": round(t_t, 4),
                       "gather": round(t_g, 4), "triad_unguarded": round(ug_t, 4),
