@@ -276,6 +276,7 @@ __global__ __launch_bounds__(SRT_BLOCK) void k_srt_keys(const int64_t* __restric
     }
 }
 
+// Digit histogram of one pass per tile of SRT_TILE keys, stored digit-major (hist[d * ntiles + t]).
 __global__ __launch_bounds__(SRT_TB) void k_srt_hist(SortBufs b, uint64_t n, uint32_t pass) {
     __shared__ uint32_t h[256];
     const uint32_t tid = threadIdx.x, shift = 8 * pass;
