@@ -141,14 +141,18 @@ def check_fault(res, log, r, seq):
 
 
 @pytest.mark.parametrize("seed,n_ranges", [(1, 200), (2, 200), (3, 200), (4, 9000),
-                                            (5, 20000)])
+                                            (5, 20000), (6, 8192 - 4 - NSLOT),
+                                            (7, 8193 - 4 - NSLOT)])
 def test_batch_against_oracle_and_alone_identity(seed, n_ranges):
     """Client tables of 200 ranges have their bucket splitters staged in LDS; tables of 9,000
-    and 20,000 ranges (more than 4,096 buckets) are searched in global memory."""
+    and 20,000 ranges (more than 4,096 buckets) are searched in global memory; tables of exactly
+    8,192 ranges (4,096 buckets, the most that are staged) and 8,193 (the fewest searched in
+    global memory) sit on either side of the boundary."""
     need_gpu()
     g, cls, reqs, P, nptrs = build(seed, n_ranges=n_ranges)
+    counts = [len(cl.rt) for cl in cls]
+    assert all(c == n_ranges + 4 + NSLOT for c in counts), counts
     if n_ranges > 8192:
-        counts = [len(cl.rt) for cl in cls]
         assert min(counts) > 8192, counts   # more than 4,096 buckets: the unstaged search
     cs = g.agile_clients_create([cl.rt for cl in cls])
     pv, po, res = run_batch(g, cs, reqs, P, nptrs)
