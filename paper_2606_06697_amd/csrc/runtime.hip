@@ -122,6 +122,7 @@ struct agile_rt {
     DevInfo info{};
     size_t lds_budget = 0;
     bool wide_only = false;  // never build narrow records (AGILE_WIDE_RECORDS=1)
+    uint32_t min_lift = 0;   // least unrolled lifting depth of the search (AGILE_MIN_LIFT)
     // two device images with their pinned staging: a table change is built into the image that
     // is not current, so launches still reading the current one are not waited for
     void* dmem = nullptr;
@@ -222,7 +223,10 @@ static uint32_t lift_levels(uint32_t rlevels) {
     return rlevels;
 }
 
-static void search_geometry(DevTable& t, const uint64_t* s64, uint32_t* radix, size_t budget) {
+// min_lift (2, 4, 6 or 8; 0 for none) raises the unrolled lifting depth for tests
+// (AGILE_MIN_LIFT): every depth variant of the packed-record search is then reachable on any table.
+static void search_geometry(DevTable& t, const uint64_t* s64, uint32_t* radix, size_t budget,
+                            uint32_t min_lift) {
     const uint32_t nb = t.nb;
     const size_t ks = t.compressed ? 4 : 8;
     t.rlog2 = 0;
@@ -257,7 +261,8 @@ static void search_geometry(DevTable& t, const uint64_t* s64, uint32_t* radix, s
             radix[nr] = ntop;
             for (uint32_t r = 0; r < nr; ++r) maxm = std::max(maxm, radix[r + 1] - radix[r]);
             const uint32_t rlevels = bitlen(maxm);
-            const uint32_t lift = lift_levels(rlevels);
+            const uint32_t lift = rlevels <= 8 ? std::max(lift_levels(rlevels), min_lift)
+                                               : lift_levels(rlevels);
             const size_t top_bytes = ((((size_t)ntop + (1ull << lift)) * ks + 15) / 16) * 16;
             const size_t need = top_bytes + (size_t)(nr + 1) * 4;
             if (need > budget) continue;
@@ -342,7 +347,7 @@ static int upload(agile_rt* rt, hipStream_t s) {
             t.shift = sh;
         }
     }
-    search_geometry(t, s64, radix, std::min(rt->lds_budget, rt->info.lds_per_block));
+    search_geometry(t, s64, radix, std::min(rt->lds_budget, rt->info.lds_per_block), rt->min_lift);
     t.nrec = im.nrec;
     if (!rt->wide_only) build_narrow(t, s64, rec, nrec);
     // the last readers of image x
@@ -484,6 +489,10 @@ int agile_rt_create(agile_rt** out, uint32_t capacity, int device) {
         if (v >= 1024) rt->lds_budget = (size_t)v;
     }
     if (const char* e = std::getenv("AGILE_WIDE_RECORDS")) rt->wide_only = std::atoi(e) != 0;
+    if (const char* e = std::getenv("AGILE_MIN_LIFT")) {
+        const int v = std::atoi(e);
+        if (v == 2 || v == 4 || v == 6 || v == 8) rt->min_lift = (uint32_t)v;
+    }
     rt->stage_bytes = image_bytes(rt->cap_nb);
     const size_t img_bytes = ((rt->stage_bytes + 255) / 256) * 256;
     const size_t dev_bytes = 2 * img_bytes + sizeof(DevLog);

@@ -135,6 +135,22 @@ def test_two_level_search_small_lds_budget(budget, monkeypatch):
     tw.close()
 
 
+@pytest.mark.parametrize("lift", ["2", "4", "6", "8"])
+@pytest.mark.parametrize("n_ranges", [64, 4096])
+def test_every_unrolled_search_depth(n_ranges, lift, monkeypatch):
+    """The packed-record search is unrolled for 2, 4, 6 and 8 lifting levels and a table picks
+    the depth its radix runs need; AGILE_MIN_LIFT raises the depth (deeper is still exact: the
+    staged splitters are followed by sentinels), so each variant runs against the oracle."""
+    need_gpu()
+    monkeypatch.setenv("AGILE_MIN_LIFT", lift)
+    tb = make_table(n_ranges, n_ranges // 8, 20 + int(lift))
+    tw = Twin(n_ranges)
+    tw.insert_table(tb)
+    q = make_queries(tb, 200_003, 20 + int(lift)).numpy().view(np.uint64)
+    assert_same(tw, q, f"{n_ranges} ranges, lift {lift}")
+    tw.close()
+
+
 @pytest.mark.parametrize("wide", ["0", "1"])
 def test_large_table_ragged_queries(wide, monkeypatch):
     """65,536 ranges (8,192 protected) and a query count that is not a multiple of any tile,
