@@ -137,7 +137,12 @@ def hostile_indices(rng, rows, n, extra_rows=()):
     return np.array(vals, dtype=np.int64)
 
 
-ROWS_CASES = [(4, 1), (4, 2), (4, 3), (4, 4), (4, 8), (4, 64), (4, 256), (8, 1), (8, 2), (8, 32)]
+# row shapes for every gather/scatter path: narrow rows (<= 16 B), rows of a part of a wave, rows of a
+# whole wave in 16-byte chunks (1 KiB), and rows of a whole wave in element-wide chunks (a row whose
+# size is not a multiple of 16 bytes and spans more than 64 elements: (4, 67), (8, 33)); (4, 100)
+# leaves 7 of its 32 lanes idle
+ROWS_CASES = [(4, 1), (4, 2), (4, 3), (4, 4), (4, 8), (4, 64), (4, 256), (8, 1), (8, 2), (8, 32),
+              (4, 67), (8, 33), (4, 100)]
 
 
 @pytest.mark.parametrize("w,D", ROWS_CASES)
