@@ -21,7 +21,9 @@ pytestmark = pytest.mark.gpu
 
 DST_ROWS = 3000
 NMAX = 70001
-CASES = [(4, 1), (4, 3), (4, 64), (4, 128), (8, 2), (8, 32)]
+# (4, 300) and (8, 70): rows wider than one column block of the reduce (256 floats in 16-byte
+# chunks, 64 doubles one per lane), so each tile is walked once per block
+CASES = [(4, 1), (4, 3), (4, 64), (4, 128), (8, 2), (8, 32), (4, 300), (8, 70)]
 
 
 def layout(w, D, rows=DST_ROWS):
