@@ -42,7 +42,7 @@ static __host__ __device__ inline uint32_t token_tag(uint64_t key, uint32_t slot
 }
 
 // One verdict; `rec` is the slot's record (read only when the slot is in range).
-static __device__ __forceinline__ uint8_t judge(uint64_t tok, uint32_t slot, uint2 rec, uint64_t key,
+static __device__ __forceinline__ uint8_t token_verdict(uint64_t tok, uint32_t slot, uint2 rec, uint64_t key,
                                          uint32_t client, uint32_t want) {
     const uint32_t gen = (uint32_t)(tok >> 16) & GEN_MASK;
     if ((uint32_t)(tok & 0xFFFFu) != token_tag(key, slot, gen)) return AGILE_TOKEN_FORGED;
@@ -56,7 +56,7 @@ static __device__ __forceinline__ uint8_t judge(uint64_t tok, uint32_t slot, uin
 
 // Grid-stride over groups of TPT tokens per thread: the token, client and kind loads are
 // coalesced, the TPT slot-record loads of a thread are issued together (random 8-byte reads of
-// an L2-resident table), then each token is judged.
+// an L2-resident table), then each token gets its verdict.
 __global__ __launch_bounds__(TBLOCK) void k_tokens_check(
     const uint2* __restrict__ recs, uint32_t cap, uint64_t key, const uint64_t* __restrict__ tok,
     const uint32_t* __restrict__ cli, const uint8_t* __restrict__ kinds, uint64_t n,
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(TBLOCK) void k_tokens_check(
         for (int j = 0; j < TPT; ++j) {
             const uint64_t i = i0 + (uint64_t)j * nth;
             if (i >= n) break;
-            const uint8_t v = s[j] < cap ? judge(t[j], s[j], r[j], key, c[j], w[j])
+            const uint8_t v = s[j] < cap ? token_verdict(t[j], s[j], r[j], key, c[j], w[j])
                                          : (uint8_t)AGILE_TOKEN_FORGED;
             __builtin_nontemporal_store(v, verdict + i);
             __builtin_nontemporal_store(v == AGILE_TOKEN_VALID ? (int32_t)s[j] : -1, slot_out + i);
@@ -188,8 +188,8 @@ int agile_token_mint(agile_tokens* ts, uint32_t client, uint32_t kind, uint64_t*
     return AGILE_OK;
 }
 
-// Host-side judgement of one token (the same rule as the device check).
-static int host_judge(const agile_tokens* ts, uint64_t tok, uint32_t client, uint32_t* slot) {
+// Host-side verdict of one token (the same rule as the device check).
+static int host_token_verdict(const agile_tokens* ts, uint64_t tok, uint32_t client, uint32_t* slot) {
     const uint32_t s = (uint32_t)(tok >> 40);
     if (s >= ts->cap) return AGILE_TOKEN_FORGED;
     *slot = s;
@@ -205,7 +205,7 @@ static int host_judge(const agile_tokens* ts, uint64_t tok, uint32_t client, uin
 int agile_token_release(agile_tokens* ts, uint64_t token, uint32_t client) {
     if (!ts) return AGILE_EINVAL;
     uint32_t s = 0;
-    if (host_judge(ts, token, client, &s) != AGILE_TOKEN_VALID) return AGILE_ENOENT;
+    if (host_token_verdict(ts, token, client, &s) != AGILE_TOKEN_VALID) return AGILE_ENOENT;
     const uint32_t gen = ts->rec[s].y >> 8;
     if (gen == GEN_MASK) {
         ts->rec[s] = make_uint2(OWNER_RETIRED, gen << 8);
