@@ -245,16 +245,23 @@ static SortBufs sort_bufs(void* scratch, uint64_t n) {
 }
 
 // Keys: guarded rows that pass the fast test get (idx - rlo); the others the sentinel. The
-// unguarded twin keys every row by idx + 2^31 (its indices must lie in [-2^31, 2^31 - 1)).
+// unguarded twin keys every row by idx + 2^31 (its indices must lie in [-2^31, 2^31 - 1)). One
+// workgroup per tile of SRT_TILE rows, which also counts the tile's digits of the first pass, so
+// the sort's first histogram needs no pass over the keys of its own.
 template <bool GUARD>
-__global__ __launch_bounds__(SRT_BLOCK) void k_srt_keys(const int64_t* __restrict__ idx, uint64_t n,
-                                                        RowsGuard rg, SortBufs b) {
-    const uint64_t tid = (uint64_t)blockIdx.x * SRT_BLOCK + threadIdx.x;
-    const uint64_t stride = (uint64_t)gridDim.x * SRT_BLOCK;
-    if (tid < CTL_WORDS) b.ctl[tid] = 0;  // every pass starts from buffer 0
-    // the loop bound is uniform per wave (i0 is the wave's first row), so ballots see all lanes
-    for (uint64_t i0 = tid & ~63ull; i0 < n; i0 += stride) {
-        const uint64_t i = i0 + (threadIdx.x & 63u);
+__global__ __launch_bounds__(SRT_TB) void k_srt_keys(const int64_t* __restrict__ idx, uint64_t n,
+                                                     RowsGuard rg, SortBufs b) {
+    __shared__ uint32_t h[256];
+    const uint32_t tid = threadIdx.x;
+    if (blockIdx.x == 0 && tid < CTL_WORDS) b.ctl[tid] = 0;  // every pass starts from buffer 0
+    if (tid < 256) h[tid] = 0;
+    __syncthreads();
+    const uint64_t t0 = (uint64_t)blockIdx.x * SRT_TILE;
+#pragma unroll
+    for (uint32_t r = 0; r < SRT_TILE / SRT_TB; ++r) {
+        // a wave covers 64 consecutive rows (i0 is its first), so its ballot is one bitmask word
+        const uint64_t i0 = t0 + r * SRT_TB + (tid & ~63u);
+        const uint64_t i = i0 + (tid & 63u);
         uint32_t key = SRT_SENT;
         bool slow = false;
         if (i < n) {
@@ -268,12 +275,15 @@ __global__ __launch_bounds__(SRT_BLOCK) void k_srt_keys(const int64_t* __restric
             }
             b.keys[0][i] = key;
             b.vals[0][i] = (uint32_t)i;
+            atomicAdd(&h[key & 255u], 1u);
         }
         if (GUARD) {
             const uint64_t m = __ballot(slow);
-            if ((threadIdx.x & 63u) == 0) b.slow[i0 >> 6] = m;
+            if ((tid & 63u) == 0 && i0 < n) b.slow[i0 >> 6] = m;
         }
     }
+    __syncthreads();
+    if (tid < 256) b.hist[(uint64_t)tid * gridDim.x + blockIdx.x] = h[tid];
 }
 
 // Digit histogram of one pass per tile of SRT_TILE keys, stored digit-major (hist[d * ntiles + t]).
@@ -632,11 +642,10 @@ static void scatter_add_sorted(const DevTable& t, DevLog* log, void* dst, uint64
                                hipStream_t s) {
     const SortBufs b = sort_bufs(scratch, n);
     const uint32_t ntiles = (uint32_t)srt_ntiles(n);
-    const uint64_t kg = (n + SRT_BLOCK - 1) / SRT_BLOCK;
-    const uint32_t kgrid = (uint32_t)(kg < (uint64_t)d.num_cu * 8 ? kg : (uint64_t)d.num_cu * 8);
-    hipLaunchKernelGGL((k_srt_keys<G>), dim3(kgrid), dim3(SRT_BLOCK), 0, s, idx, n, rg, b);
+    // the key pass also writes the first pass's per-tile histograms
+    hipLaunchKernelGGL((k_srt_keys<G>), dim3(ntiles), dim3(SRT_TB), 0, s, idx, n, rg, b);
     for (uint32_t p = 0; p < npasses; ++p) {
-        hipLaunchKernelGGL(k_srt_hist, dim3(ntiles), dim3(SRT_TB), 0, s, b, n, p);
+        if (p > 0) hipLaunchKernelGGL(k_srt_hist, dim3(ntiles), dim3(SRT_TB), 0, s, b, n, p);
         hipLaunchKernelGGL(k_srt_scan_rows, dim3(256), dim3(SRT_BLOCK), 0, s, b, ntiles);
         hipLaunchKernelGGL(k_srt_scatter, dim3(ntiles), dim3(SRT_TB), 0, s, b, n, p);
     }
