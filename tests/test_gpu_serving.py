@@ -63,9 +63,11 @@ def test_serving_mix_equals_alone():
     srv.close()
 
 
-def _copy_burst(budget, ring, copy_range):
+def _copy_burst(budget, ring, copy_range, oversize=()):
     """400-odd copy requests from 6 clients arriving within 2 ms, at most 4 per launch and 4
-    launches in flight; returns the server, the arrival times and the run's outputs."""
+    launches in flight; the requests at positions `oversize` copy 2 MiB, more than the budget
+    or the ring can ever hold, and must be refused without a launch. Returns the server, the
+    request count and the run's statistics."""
     from paper_2606_06697_amd.serving import Server, ServeConfig
     from synth import make_serving_trace
     cfg = ServeConfig(n_clients=6, rate=200000.0, duration=0.002, ranges=(256, 1024),
@@ -79,14 +81,18 @@ def _copy_burst(budget, ring, copy_range):
                                gather_range=cfg.gather_range)
     n = trace["t"].numel()
     assert n > 300
+    big = np.zeros(n, dtype=bool)
+    big[list(oversize)] = True
+    trace["size"][torch.from_numpy(big)] = 2 << 20
     rng = np.random.default_rng(3)
-    sample = set(rng.choice(n, size=100, replace=False).tolist())
+    sample = set(rng.choice(np.flatnonzero(~big), size=100, replace=False).tolist())
     lat, stats, kept = srv.run(trace, record=sample)
-    assert stats["requests"] == n and stats["refused"] == 0 and not np.isnan(lat).any()
+    assert stats["requests"] == n - big.sum() and stats["refused"] == big.sum()   # served / refused
+    assert np.array_equal(srv.refused, big) and not np.isnan(lat[~big]).any()
     arr = trace["t"].numpy()
-    assert (srv.t_launch >= arr).all()
+    assert (srv.t_launch[~big] >= arr[~big]).all()
     # admitted as earlier launches returned their output space, not all at once
-    assert (srv.t_launch > float(np.min(arr + lat))).sum() > n // 4
+    assert (srv.t_launch[~big] > float(np.min(arr[~big] + lat[~big]))).sum() > n // 4
     check_against_alone_and_oracle(srv, kept)
     return srv, n, stats
 
@@ -96,14 +102,16 @@ def test_serving_admission_waits_for_the_hbm_budget():
     no two requests fit the budget together, so each launch carries one request, only one
     launch is ever in flight, and the FIFO head waits for the budget (counted per request)
     while the launch before it holds its bytes. Sampled results equal the request run alone
-    and the oracle."""
+    and the oracle. Five 2 MiB copies, which no budget of 1.75 MiB can ever admit, are refused
+    without a launch and do not hold up the requests behind them."""
     need_gpu()
     guard_mod()
     budget = 1792 << 10
-    srv, n, stats = _copy_burst(budget, 64 << 20, (1 << 20, 1536 << 10))
+    srv, n, stats = _copy_burst(budget, 64 << 20, (1 << 20, 1536 << 10),
+                                oversize=(3, 50, 51, 200, 300))
     assert stats["budget_waits"] > 0 and stats["ring_waits"] == 0, stats
     assert 1 << 20 <= stats["max_inflight_bytes"] <= budget, stats
-    assert stats["max_concurrent_launches"] == 1 and stats["launches"] == n, stats
+    assert stats["max_concurrent_launches"] == 1 and stats["launches"] == n - 5, stats
     srv.close()
 
 
