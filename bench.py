@@ -367,8 +367,13 @@ def time_blocks(calls, warmup, reps):
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     out = {}
     for name, fn in calls.items():
+        setup = None
+        if isinstance(fn, tuple):  # (untimed set-up before each launch, the timed launch)
+            setup, fn = fn
         ts = []
         for rep in range(warmup + reps):
+            if setup is not None:
+                setup()
             e0.record()
             fn()
             e1.record()
@@ -571,10 +576,14 @@ def bench_embedding(g, args):
         "backward_unguarded": lambda: g.agile_unguarded_scatter(dWbuf, rb, idx, dY, N, 0, 1),
         "torch_index_select": lambda: torch.index_select(W2, 0, idx_m, out=Y2),
         "torch_index_add": lambda: dW2.index_add_(0, idx_m, dY_m),
+        # the autograd path: a zeroed gradient (zeroed before each launch, untimed), summed
+        # into without reading its rows
+        "backward_into_zeros": (dW.zero_, lambda: g.agile_guarded_scatter(
+            t.handle, dW, rb, idx, dY, N, 0, g.SCATTER_ADD_INTO_ZEROS)),
     }, 2, 10)
     rc, f = t.fault_log(clear=True)
     nbad = int(((ih < 0) | (ih >= R)).sum())
-    calls_guarded = 2 * 12
+    calls_guarded = 3 * 12
     assert int(f["count"]) == nbad * D * calls_guarded, (int(f["count"]), nbad)
     t.close()
     med = {k: float(np.median(v)) for k, v in ts.items()}
@@ -589,6 +598,8 @@ def bench_embedding(g, args):
            "forward_unguarded_gbps": round(fwd_bytes / med["forward_unguarded"] / 1e6, 1),
            "forward_rows_per_s": round(N / (med["forward"] / 1e3), 1),
            "backward_gbps": round(bwd_bytes / med["backward"] / 1e6, 1),
+           "backward_into_zeros_gbps": round((N * (8 + rb) + distinct * rb)
+                                             / med["backward_into_zeros"] / 1e6, 1),
            "backward_unguarded_gbps": round(bwd_bytes / med["backward_unguarded"] / 1e6, 1),
            "distinct_rows": distinct, "hostile_idx": nbad,
            "faults_per_call": int(f["count"]) // calls_guarded}

@@ -254,7 +254,11 @@ int agile_guarded_gather(agile_rt* rt, void* d_out, const void* d_table, uint64_
                          void* stream);
 
 /* dst[idx[i], :] = src[i, :] (accumulate == 0; with duplicate indices one writer wins) or
- * dst[idx[i], :] += src[i, :] (accumulate == 1). With accumulate, calls of at least 32,768
+ * dst[idx[i], :] += src[i, :] (accumulate == 1). accumulate == 2 is accumulate == 1 for a
+ * destination whose rows are all +0.0 before the call (a fresh gradient, for instance): the
+ * result is the same bit for bit, and large calls then write each row's sum without reading
+ * the row; on any other destination the result is unspecified. Other values: AGILE_EINVAL.
+ * With accumulate, calls of at least 32,768
  * rows sort the destination rows (scratch owned by the handle, grown on demand with
  * hipMalloc, freed by agile_rt_destroy; ENOMEM never results: without scratch the call takes
  * the chunk path) and sum each run of equal rows in index order; the order in which partial
@@ -273,8 +277,8 @@ int agile_fault_log_read(agile_rt* rt, agile_fault* out, int clear, void* stream
 
 /* ---- unguarded twins (same kernels with the guard compiled out; measurement only) ----
  * Every access is performed as addressed: the caller guarantees the arguments are valid.
- * agile_unguarded_scatter with accumulate == 1 and n >= 32,768 sorts 32-bit keys idx + 2^31,
- * so its indices must lie in [-2^31, 2^31 - 1); its sort scratch is one buffer per device
+ * agile_unguarded_scatter with accumulate (1 or 2, as above) and n >= 32,768 sorts 32-bit
+ * keys idx + 2^31, so its indices must lie in [-2^31, 2^31 - 1); its sort scratch is one buffer per device
  * (grown on demand), so such calls on one device must be ordered. */
 int agile_unguarded_copy(void* d_dst, const void* d_src, uint64_t nbytes, void* stream);
 int agile_unguarded_triad(float* d_a, const float* d_b, const float* d_c, float s, uint64_t n,

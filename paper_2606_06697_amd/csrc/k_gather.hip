@@ -383,7 +383,7 @@ hipError_t launch_scatter(bool guard, const DevTable& t, DevLog* log, const Bind
     if (n == 0) return hipSuccess;
     if (accumulate)
         return launch_scatter_add(guard, t, log, binds, dst, rb, idx, src, n, w, seq, logon,
-                                  scratch, d, s, finish);
+                                  scratch, d, s, finish, accumulate == 2);
     if (guard) {
         const RowsGuard rg = rows_guard(binds[0], binds[1], binds[2], (uint64_t)idx, (uint64_t)src,
                                         (uint64_t)dst, n, rb, w);

@@ -504,10 +504,13 @@ __device__ __forceinline__ void srt_flush(uint8_t* dst, uint64_t rb, int64_t row
 // summed in order. A run the tile owns ends with a plain store of (destination + sum); a run
 // shared with a neighbouring tile ends with one atomic add per element.
 constexpr int RED_U = 8;
+// zero_dst: the destination rows are +0.0 before the call (the caller's promise), so the rows are
+// not read: an owned run stores (+0.0 + sum), exactly what the read-modify-write would.
 template <bool GUARD, int W, int EPL>
 __global__ __launch_bounds__(256) void k_srt_reduce(uint8_t* dst, uint64_t rb,
                                                     const uint8_t* __restrict__ src, uint64_t n,
-                                                    SortBufs b, uint32_t npasses, int64_t rlo) {
+                                                    SortBufs b, uint32_t npasses, int64_t rlo,
+                                                    uint32_t zero_dst) {
     using F = typename FloatOf<W>::F;
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t wave = ((uint64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
@@ -543,7 +546,9 @@ __global__ __launch_bounds__(256) void k_srt_reduce(uint8_t* dst, uint64_t rb,
             uint32_t cur = k0;
             bool first = true, stop = false;
             RowVec<W, EPL> dcur;
-            if (on && !head_shared)
+#pragma unroll
+            for (int q = 0; q < EPL; ++q) dcur.v[q] = (F)0.0;
+            if (on && !head_shared && !zero_dst)
                 dcur = load_row<W, EPL>(dst + (uint64_t)(base + (int64_t)k0) * rb, rb, 0, col0);
 #pragma unroll
             for (int j = 0; j < RED_TILE / 64; ++j) {
@@ -560,9 +565,15 @@ __global__ __launch_bounds__(256) void k_srt_reduce(uint8_t* dst, uint64_t rb,
                         if (kk[u] != SRT_SENT && on) {
                             rv[u] = load_row<W, EPL, true>(src, rb, vv[u], col0);
                             const uint32_t prev = u == 0 ? cur : kk[u - 1];
-                            if (kk[u] != prev)
-                                dv[u] = load_row<W, EPL>(dst + (uint64_t)(base + (int64_t)kk[u]) * rb,
-                                                         rb, 0, col0);
+                            if (kk[u] != prev) {
+                                if (zero_dst) {
+#pragma unroll
+                                    for (int q = 0; q < EPL; ++q) dv[u].v[q] = (F)0.0;
+                                } else {
+                                    dv[u] = load_row<W, EPL>(
+                                        dst + (uint64_t)(base + (int64_t)kk[u]) * rb, rb, 0, col0);
+                                }
+                            }
                         }
                     }
 #pragma unroll
@@ -639,7 +650,7 @@ static void scatter_add_sorted(const DevTable& t, DevLog* log, void* dst, uint64
                                const int64_t* idx, const void* src, uint64_t n,
                                const RowsGuard& rg, uint32_t npasses, void* scratch,
                                unsigned long long seq, int logon, const DevInfo& d,
-                               hipStream_t s) {
+                               hipStream_t s, bool zero_dst) {
     const SortBufs b = sort_bufs(scratch, n);
     const uint32_t ntiles = (uint32_t)srt_ntiles(n);
     // the key pass also writes the first pass's per-tile histograms
@@ -655,10 +666,10 @@ static void scatter_add_sorted(const DevTable& t, DevLog* log, void* dst, uint64
     const bool v4 = W == 4 && (rb / W) % 4 == 0 && (((uint64_t)src | (uint64_t)dst | rb) & 15) == 0;
     if (v4)
         hipLaunchKernelGGL((k_srt_reduce<G, W, 4>), dim3(rgrid), dim3(256), 0, s, (uint8_t*)dst, rb,
-                           (const uint8_t*)src, n, b, npasses, rg.g.rlo);
+                           (const uint8_t*)src, n, b, npasses, rg.g.rlo, (uint32_t)zero_dst);
     else
         hipLaunchKernelGGL((k_srt_reduce<G, W, 1>), dim3(rgrid), dim3(256), 0, s, (uint8_t*)dst, rb,
-                           (const uint8_t*)src, n, b, npasses, rg.g.rlo);
+                           (const uint8_t*)src, n, b, npasses, rg.g.rlo, (uint32_t)zero_dst);
     if (G) {
         const uint64_t sw = (n + 63) / 64;
         const uint64_t sb = (sw + 3) / 4;
@@ -687,7 +698,8 @@ static void scatter_add_w(const DevTable& t, DevLog* log, void* dst, uint64_t rb
 hipError_t launch_scatter_add(bool guard, const DevTable& t, DevLog* log, const Bind* binds,
                               void* dst, uint64_t rb, const int64_t* idx, const void* src,
                               uint64_t n, uint32_t w, unsigned long long seq, int logon,
-                              void* scratch, const DevInfo& d, hipStream_t s, bool finish) {
+                              void* scratch, const DevInfo& d, hipStream_t s, bool finish,
+                              bool zero_dst) {
     if (n == 0) return hipSuccess;
     const RowsGuard rg = guard ? rows_guard(binds[0], binds[1], binds[2], (uint64_t)idx,
                                             (uint64_t)src, (uint64_t)dst, n, rb, w)
@@ -714,11 +726,11 @@ hipError_t launch_scatter_add(bool guard, const DevTable& t, DevLog* log, const 
     }
     if (sorted) {
         if (guard) {
-            if (w == 4) scatter_add_sorted<true, 4>(t, log, dst, rb, idx, src, n, rg, npasses, scratch, seq, logon, d, s);
-            else scatter_add_sorted<true, 8>(t, log, dst, rb, idx, src, n, rg, npasses, scratch, seq, logon, d, s);
+            if (w == 4) scatter_add_sorted<true, 4>(t, log, dst, rb, idx, src, n, rg, npasses, scratch, seq, logon, d, s, zero_dst);
+            else scatter_add_sorted<true, 8>(t, log, dst, rb, idx, src, n, rg, npasses, scratch, seq, logon, d, s, zero_dst);
         } else {
-            if (w == 4) scatter_add_sorted<false, 4>(t, log, dst, rb, idx, src, n, rg, npasses, scratch, seq, logon, d, s);
-            else scatter_add_sorted<false, 8>(t, log, dst, rb, idx, src, n, rg, npasses, scratch, seq, logon, d, s);
+            if (w == 4) scatter_add_sorted<false, 4>(t, log, dst, rb, idx, src, n, rg, npasses, scratch, seq, logon, d, s, zero_dst);
+            else scatter_add_sorted<false, 8>(t, log, dst, rb, idx, src, n, rg, npasses, scratch, seq, logon, d, s, zero_dst);
         }
     } else if (guard) {
         if (w == 4) scatter_add_w<true, 4>(t, log, dst, rb, idx, src, n, rg, seq, logon, d, s);

@@ -47,10 +47,13 @@ hipError_t launch_scatter(bool guard, const DevTable& t, DevLog* log, const Bind
                           uint32_t w, int accumulate, unsigned long long seq, int logon,
                           void* scratch, const DevInfo& d, hipStream_t s, bool finish = true);
 
+// zero_dst: the destination rows are +0.0 before the call (scatter-add mode 2); the sorted path
+// then writes each row's sum without reading the row.
 hipError_t launch_scatter_add(bool guard, const DevTable& t, DevLog* log, const Bind* binds,
                               void* dst, uint64_t rb, const int64_t* idx, const void* src,
                               uint64_t n, uint32_t w, unsigned long long seq, int logon,
-                              void* scratch, const DevInfo& d, hipStream_t s, bool finish = true);
+                              void* scratch, const DevInfo& d, hipStream_t s, bool finish = true,
+                              bool zero_dst = false);
 
 size_t scatter_add_scratch_bytes(uint64_t n);
 

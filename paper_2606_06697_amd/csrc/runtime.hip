@@ -873,7 +873,7 @@ int agile_guarded_gather(agile_rt* rt, void* d_out, const void* d_table, uint64_
 static int scatter_impl(agile_rt* rt, void* d_dst, uint64_t row_bytes, const int64_t* d_idx,
                         const void* d_src, uint64_t n, int dtype, int accumulate, int policy,
                         void* stream, bool noalloc) {
-    if (!rt || !policy_ok(policy) || (accumulate != 0 && accumulate != 1)) return AGILE_EINVAL;
+    if (!rt || !policy_ok(policy) || accumulate < 0 || accumulate > 2) return AGILE_EINVAL;
     if (rt->retired) return AGILE_ETRAPPED;
     Redirect rd;
     if (redirecting(policy) && redirect_of(rt, policy, &rd) != AGILE_OK) return AGILE_EINVAL;
@@ -1202,7 +1202,7 @@ int agile_unguarded_scatter(void* d_dst, uint64_t row_bytes, const int64_t* d_id
                             const void* d_src, uint64_t n, int dtype, int accumulate,
                             void* stream) {
     uint32_t w;
-    if (accumulate != 0 && accumulate != 1) return AGILE_EINVAL;
+    if (accumulate < 0 || accumulate > 2) return AGILE_EINVAL;
     int rc = rows_args_ok(row_bytes, n, dtype, d_dst, d_src, &w);
     if (rc != AGILE_OK) return rc;
     if (n && (!d_dst || !d_src || !d_idx)) return AGILE_EINVAL;

@@ -67,8 +67,9 @@ class GuardedEmbeddingFunction(torch.autograd.Function):
         rb = D * dW.element_size()
         ids = _registered(table, [dW, dY])
         try:
+            # dW was just zeroed: its rows are summed into without being read
             g.agile_guarded_scatter(table.handle, dW, rb, idx, dY, idx.numel(),
-                                    _DTYPES[ctx.wdtype], 1, ctx.policy)
+                                    _DTYPES[ctx.wdtype], g.SCATTER_ADD_INTO_ZEROS, ctx.policy)
         finally:
             for rid in ids:
                 table.remove(rid)

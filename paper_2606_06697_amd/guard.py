@@ -29,6 +29,9 @@ ALLOW, V_PROTECTED, V_STRADDLE, V_UNMAPPED, V_CROSS_ALLOC, V_INEXACT = 0, 1, 2, 
  POLICY_REMAP) = 0, 1, 2, 3, 4, 5
 OP_COPY, OP_TRIAD, OP_GATHER, OP_SCATTER, OP_SCATTER_ADD = 1, 2, 3, 4, 5
 DTYPE_F32, DTYPE_F64 = 0, 1
+# agile_guarded_scatter's `accumulate`: plain scatter, scatter-add, scatter-add into a destination
+# whose rows are all +0.0 before the call (same result, the sorted path skips reading the rows)
+SCATTER, SCATTER_ADD, SCATTER_ADD_INTO_ZEROS = 0, 1, 2
 TOKEN_VALID, TOKEN_FORGED, TOKEN_STALE, TOKEN_CROSS_CLIENT, TOKEN_WRONG_KIND = 0, 1, 2, 3, 4
 TOKEN_ANY_KIND = 255
 NO_SEQ = (1 << 64) - 1

@@ -76,7 +76,7 @@ def test_argument_errors_fail_closed(L):
     assert L.agile_unguarded_gather(0, 0, 4, 0, 1, 9, 0) == g.AGILE_EINVAL
     assert L.agile_unguarded_gather(0, 0, 0, 0, 1, 0, 0) == g.AGILE_EINVAL
     assert L.agile_unguarded_gather(0, 0, 6, 0, 1, 0, 0) == g.AGILE_EINVAL
-    assert L.agile_unguarded_scatter(0, 4, 0, 0, 1, 0, 2, 0) == g.AGILE_EINVAL
+    assert L.agile_unguarded_scatter(0, 4, 0, 0, 1, 0, 3, 0) == g.AGILE_EINVAL
     # apertures: null handles and empty apertures are rejected before any HIP call
     assert "virtual memory" in g.strerror(g.AGILE_ENOTSUP)
     ok3 = (ctypes.c_uint64 * 3)(1, 1, 1)

@@ -137,6 +137,35 @@ def test_sorted_scatter_add_last_row_of_a_power_of_two_table(w, D, rows, hostile
     tw.close()
 
 
+@pytest.mark.parametrize("w,D", [(4, 64), (4, 3), (8, 2), (4, 300)])
+def test_scatter_add_into_zeros(w, D):
+    """accumulate == 2 (the destination's rows are +0.0 before the call, as for a fresh
+    gradient): on the sorted path the rows are written without being read, and the arena and
+    the log equal the oracle's scatter-add into the same zeroed destination byte for byte, with
+    hot rows, hostile indices and an interior destination pointer (negative indices)."""
+    ar, tw, off = setup(w, D, 500 + D + w)
+    rb = w * D
+    dtype = 0 if w == 4 else 1
+    dt = np.float32 if w == 4 else np.float64
+    ol = G.FaultLog()
+    rng = random.Random(600 + D + w)
+    base = ar.addr(off["dst"][0])
+    hostile_rows = [(ar.addr(off["prot"][0]) - base) // rb + 1,
+                    (ar.addr(off["other"][0]) - base) // rb + 2]
+    for t, (dst, n, neg) in enumerate(((base, 40000, 0), (base + 100 * rb, 50001, 100))):
+        ar.write(off["dst"][0], np.zeros(DST_ROWS * D, dtype=dt))
+        rows = DST_ROWS - 101 if neg else DST_ROWS
+        idx = indices(rng, n, rows, hostile_rows, neg)
+        ar.write(off["idx"][0], idx)
+        tw.g.agile_guarded_scatter(tw.h, dst, rb, ar.addr(off["idx"][0]), ar.addr(off["src"][0]),
+                                   n, dtype, tw.g.SCATTER_ADD_INTO_ZEROS)
+        G.scatter_vec(tw.ot, ar.mem, ol, tw.next_seq(), dst, rb, ar.addr(off["idx"][0]),
+                      ar.addr(off["src"][0]), n, w, True)
+        ar.check(f"scatter-add into zeros w={w} D={D} trial {t}")
+        log_matches(tw, ol, f"scatter-add into zeros w={w} D={D} trial {t}")
+    tw.close()
+
+
 @pytest.mark.parametrize("w,D", [(4, 64), (8, 2)])
 def test_unguarded_sorted_scatter_add_matches_guarded(w, D):
     ar, tw, off = setup(w, D, 77 + D)
