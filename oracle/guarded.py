@@ -47,7 +47,9 @@ Access widths and orders: copy - bytes, src(0) then dst(1); triad ``a = b + s*c`
 elements, b(0), c(1), a(2), computed as two float32 roundings (no fused multiply-add);
 gather ``out[i,:] = T[idx[i],:]`` - the 8-byte index load (elem ``i*D``), then per column
 the table element (1) and the out element (2); scatter ``dst[idx[i],:] = src[i,:]`` (or
-``+=``) - idx(0), src(1), dst(2). ``D = row_bytes / w``.
+``+=``) - idx(0), src(1), dst(2). ``D = row_bytes / w``. Scatter-add into a destination whose rows
+are all +0.0 (the library's ``accumulate == 2``) is scatter-add on that destination: the oracle
+takes any true ``accumulate`` as ``+=``, and its callers zero the destination first.
 
 Each kernel comes twice: ``*_loop`` walks every access in program order (the definition,
 for small inputs) and ``*_vec`` computes the same result with numpy masks (pinned against
