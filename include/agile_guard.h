@@ -167,7 +167,13 @@ typedef struct {
 
 /* Create an empty table for up to `capacity` ranges (1 <= capacity <= 2^26) on HIP device
  * `device`; allocates its device image, fault log and pinned staging. *out receives the
- * handle. Errors: EINVAL, ENOMEM, EDEVICE. */
+ * handle. Errors: EINVAL, ENOMEM, EDEVICE.
+ * Three environment variables, read here once per handle, choose among equivalent search
+ * layouts (for tests and measurement; no verdict, owner or fault record depends on them):
+ * AGILE_LDS_BUDGET=<bytes, at least 1024> caps the LDS the validation's search index may use
+ * (default 160 KiB; a smaller budget stages fewer splitters); AGILE_WIDE_RECORDS=1 uses the
+ * general 32-byte bucket records even where packed 16-byte ones fit; AGILE_MIN_LIFT=2|4|6|8
+ * searches at least that many unrolled levels. Other values are ignored. */
 int agile_rt_create(agile_rt** out, uint32_t capacity, int device);
 
 /* Destroy a handle after all work queued with it has completed (the call synchronizes the
