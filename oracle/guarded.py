@@ -218,8 +218,9 @@ def triad_loop(table, mem, log, seq, a, b, c, s, n, policy=SUPPRESS_LOG, quarant
             else:
                 vals.append(_f32(deny.load(mem, A, 4, bind)))
                 deny(i, op_i, A, 4)
-        prod = np.float32(s32 * vals[1])          # first rounding
-        r = np.float32(vals[0] + prod)            # second rounding
+        with np.errstate(over="ignore", invalid="ignore"):   # IEEE overflow to inf / NaN is the result
+            prod = np.float32(s32 * vals[1])          # first rounding
+            r = np.float32(vals[0] + prod)            # second rounding
         A = a + 4 * i
         if _allowed(ba, A, 4):
             mem.write(A, np.float32(r).tobytes())
@@ -357,7 +358,8 @@ def triad_vec(table, mem, log, seq, a, b, c, s, n, policy=SUPPRESS_LOG):
         nden += bad.size
         if bad.size:
             cands.append((int(bad[0]), op_i, p + 4 * int(bad[0])))
-    r = (vals[0] + (np.float32(s) * vals[1]).astype(np.float32)).astype(np.float32)
+    with np.errstate(over="ignore", invalid="ignore"):   # IEEE overflow to inf / NaN is the result
+        r = (vals[0] + (np.float32(s) * vals[1]).astype(np.float32)).astype(np.float32)
     bind = table.binding(a)
     dlo, dhi = _window(a, bind)
     ok = (i >= dlo) & (i + 4 <= dhi)

@@ -20,7 +20,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 def read_fixture():
     rows = []
-    for line in open(os.path.join(HERE, "golden", "table1_apertures.txt")):
+    with open(os.path.join(HERE, "golden", "table1_apertures.txt")) as fh:
+        lines = fh.readlines()
+    for line in lines:
         line = line.split("#", 1)[0].split()
         if line:
             a, L, v, o = line
