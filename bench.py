@@ -48,7 +48,8 @@ def parse():
     p.add_argument("--counters-pass", action="store_true",
                    help="only launch each large-table kernel a few times, plus a plain 1 GiB copy "
                         "(the reference for scaling HBM counters), for a rocprofv3 --pmc run")
-    p.add_argument("--extra", choices=("small_guard", "tokens", "embedding", "batch"),
+    p.add_argument("--extra", choices=("small_guard", "tokens", "embedding", "batch",
+                                       "serving_capacity"),
                    help="run only this workload, then a plain 1 GiB copy (the reference for "
                         "scaling HBM counters), and print its JSON object")
     p.add_argument("--queries-log2", type=int, default=28, help=argparse.SUPPRESS)
@@ -77,7 +78,8 @@ def main():
     if args.extra:
         fn = {"small_guard": bench_small_guard, "tokens": bench_tokens,
               "embedding": lambda g_: bench_embedding(g_, args),
-              "batch": lambda g_: bench_batch(g_, args)}[args.extra]
+              "batch": lambda g_: bench_batch(g_, args),
+              "serving_capacity": lambda g_: bench_serving_capacity(g_, args)}[args.extra]
         out = fn(g)
         torch.cuda.empty_cache()
         ref_a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
@@ -696,6 +698,33 @@ def bench_serving(g, args):
     stats["workload"] = (f"64 clients, Poisson 20000 req/s for {cfg.duration:g} s, "
                          "50/30/20 validate/copy/gather")
     return stats
+
+
+def bench_serving_capacity(g, args):
+    """The serving workload's server (64 clients, same mix and tables) offered more load: 2 s
+    Poisson traces at 20,000 to 1,600,000 requests/s. Completed requests/s stops following the
+    offered rate where the loop saturates; latency is arrival to completion (host clock)."""
+    from paper_2606_06697_amd.serving import Server, ServeConfig
+    from synth import make_serving_trace
+
+    cfg = ServeConfig(duration=2.0)
+    srv = Server(cfg)
+    rows = []
+    for rate in (20000.0, 50000.0, 100000.0, 200000.0, 400000.0, 800000.0, 1600000.0):
+        trace = make_serving_trace(cfg.n_clients, rate, cfg.duration, cfg.seed, mix=cfg.mix,
+                                   val_ptrs=cfg.val_ptrs, copy_range=cfg.copy_range,
+                                   gather_range=cfg.gather_range)
+        _, st, _ = srv.run(trace)
+        rows.append({"offered_per_s": rate, "requests": st["requests"],
+                     "completed_per_s": round(st["requests_per_s"], 1),
+                     "latency_p50_ms": round(st["latency_p50_ms"], 4),
+                     "latency_p99_ms": round(st["latency_p99_ms"], 4),
+                     "mean_batch": round(st["mean_batch"], 2), "launches": st["launches"],
+                     "moved_gb_per_s": round(st["moved_gb_per_s"], 1), "refused": st["refused"]})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    srv.close()
+    return {"workload": "64 clients, 50/30/20 validate/copy/gather, 2 s Poisson traces at "
+                        "increasing offered rates", "rates": rows}
 
 
 def _pool_validate_worker(args):
