@@ -12,7 +12,8 @@
 // destination row, position ascending. Each wave then walks a tile of 256 sorted entries and sums the source rows
 // of each run of equal keys in position order; a run that lies wholly inside the tile owns its
 // destination row and adds with a plain read-modify-write, a run that crosses a tile boundary
-// adds with one atomic per element. Rows that failed the fast test follow in a separate kernel
+// adds with one atomic per element. When the caller promises a destination of +0.0 rows (scatter-
+// add into zeros), an owned run stores (+0.0 + its sum) without reading the row. Rows that failed the fast test follow in a separate kernel
 // that checks every element exactly (denied loads read zero, denied stores are dropped) and
 // counts denials as the other data-dependent guarded kernels do; a one-thread kernel after the
 // launch records the smallest key.
